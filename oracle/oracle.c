@@ -1084,12 +1084,14 @@ void or_explicit_L(const or_grid *G, double **prim, double **E, double **face, c
 
 /* ------------------------------------------------------------------------- */
 /* resistivity of a cell: uniform, or eta = 1/sigma_c with eq. sigma_D,
- * sigma_c = sigma_0 max(1 - D_atmo/D, 0)^2, D_atmo = rho_atm, clamped to
- * [eta_min, eta_max] */
+ * sigma_c = sigma_0 max(1 - D_atmo/D, 0)^2, clamped to [eta_min, eta_max].
+ * Reading: D_atmo is the density below which a cell is atmosphere,
+ * atm_factor rho_atm, so that the conductivity falls continuously to zero
+ * where the atmosphere begins. */
 static double or_eta(const or_grid *G, double Dund)
 {
     if (G->eta_mode == 0) return G->eta;
-    double x = 1.0 - G->rho_atm / Dund;
+    double x = 1.0 - G->rho_atm * G->atm_factor / Dund;
     if (x < 0.0) x = 0.0;
     double sig = G->sigma0 * x * x;
     if (sig * G->eta_max <= 1.0) return G->eta_max;

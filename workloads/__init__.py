@@ -225,19 +225,20 @@ def tov_profile(K=100.0, Gamma=2.0, rho_c=1.28e-3, nr=20000):
         return rho + p / (Gamma - 1.0)
 
     def rhs(r, y):
-        m, p, nu, lnr = y
+        # y = (m, p, nu, ln(rbar / r)); the last one is regular at the centre
+        m, p, nu, lnq = y
         if p <= 0:
             return np.zeros(4)
         e = eos_e(p)
         dpdr = -(e + p) * (m + 4 * math.pi * r ** 3 * p) / (r * (r - 2 * m))
         dm = 4 * math.pi * r ** 2 * e
         dnu = 2 * (m + 4 * math.pi * r ** 3 * p) / (r * (r - 2 * m))
-        dlnr = 1.0 / (r * math.sqrt(1 - 2 * m / r))
-        return np.array([dm, dpdr, dnu, dlnr])
+        dlnq = (1.0 / math.sqrt(1 - 2 * m / r) - 1.0) / r
+        return np.array([dm, dpdr, dnu, dlnq])
 
     p_c = K * rho_c ** Gamma
     r = 1e-6
-    y = np.array([4.0 / 3.0 * math.pi * r ** 3 * eos_e(p_c), p_c, 0.0, math.log(r)])
+    y = np.array([4.0 / 3.0 * math.pi * r ** 3 * eos_e(p_c), p_c, 0.0, 0.0])
     h = 20.0 / nr
     rs, ys = [r], [y.copy()]
     while y[1] > 0 and r < 50:
@@ -262,11 +263,11 @@ def tov_profile(K=100.0, Gamma=2.0, rho_c=1.28e-3, nr=20000):
     rs = np.array(rs)
     ys = np.array(ys)
     R, M = rs[-1], ys[-1, 0]
-    # isotropic radius: ln rbar = ln r + const, matched at the surface
+    # isotropic radius: ln(rbar/r) + const, matched to the exterior at the surface
     Rbar = 0.5 * (R - M + math.sqrt(R * R - 2 * M * R))
-    lnrbar = ys[:, 3] - ys[-1, 3] + math.log(Rbar)
-    rbar = np.exp(lnrbar)
-    psi_in = np.sqrt(rs / rbar)
+    lnq = ys[:, 3] - ys[-1, 3] + math.log(Rbar / R)
+    rbar = rs * np.exp(lnq)
+    psi_in = np.exp(-0.5 * lnq)
     nu_in = ys[:, 2] - ys[-1, 2] + math.log(1 - 2 * M / R)
     alpha_in = np.exp(0.5 * nu_in)
     p_in = ys[:, 1]
