@@ -1,0 +1,152 @@
+/*
+ * grmhd.h -- C ABI of the MI355X (gfx950) library for one implicit-explicit
+ * Runge-Kutta step of special/general-relativistic resistive MHD on a fixed
+ * (Cowling) Cartesian grid, after Cheong et al., arXiv:2110.03732.
+ *
+ * All arithmetic is FP64.  All array arguments named *_dev are DEVICE
+ * pointers owned by the caller; *_host arguments are host pointers read
+ * during the call.  Every call is asynchronous on the given stream unless
+ * it says it synchronises.  The library never allocates device memory in
+ * these calls: stage storage lives in the caller's workspace.
+ *
+ * Layouts (shared with the caller):
+ *   - cell arrays have N_d = n_d + 2 ng points per active direction (1 for an
+ *     inactive one), x fastest: index i + Nx (j + Ny k).  A "field block"
+ *     holds F such arrays back to back, field f starting at f * stride with
+ *     stride = gr_field_stride(grid) doubles (>= Nx Ny Nz, 256-byte aligned);
+ *   - q: 8 fields, the densitised conserved variables of Sec 2.1,
+ *     (q_D, q_S_x, q_S_y, q_S_z, q_tau, q_E^x, q_E^y, q_E^z), q = psi^6 (...);
+ *   - face: 3 fields, face-centred q_B^d = psi^6 B^d (Sec 3.2); field d at
+ *     index (i,j,k) sits half a cell below the cell centre in direction d;
+ *   - prim: 5 fields (rho, u~^x, u~^y, u~^z, p), u~^i = W v^i (Sec 2.4);
+ *   - metric: NULL (flat) or 2 fields (lapse alpha, conformal factor psi) of
+ *     a static conformally flat metric, gamma_ij = psi^4 delta_ij, beta = 0.
+ *   - an edge array (vector potential A_k) is one point longer than a cell
+ *     array in every active direction; A_k at (i,j,k) sits half a cell below
+ *     the cell centre in the two directions other than k.
+ *
+ * Errors: host-detectable problems return a negative gr_status; numerical
+ * trouble inside a cell never fails a call: the cell falls back to the
+ * atmosphere state and a device counter is incremented (gr_fail_count).
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GR_ABI_VERSION 1
+
+typedef enum {
+    GR_OK = 0,
+    GR_EINVAL = -1,        /* bad argument, shape or parameter            */
+    GR_ENOMEM = -2,        /* workspace too small                         */
+    GR_EHIP = -3,          /* a HIP runtime call or kernel launch failed   */
+    GR_EUNSUPPORTED = -4   /* valid but not implemented (e.g. xi != 0)    */
+} gr_status;
+
+enum { GR_OUTFLOW = 0, GR_PERIODIC = 1, GR_FIXED = 2 };   /* boundary rules  */
+enum { GR_MINMOD = 0, GR_MC = 1, GR_PPM = 2 };             /* reconstruction  */
+enum { GR_SSP2_222 = 0, GR_SSP3_433 = 1 };                 /* IMEX tableaux   */
+enum { GR_ETA_UNIFORM = 0, GR_ETA_SIGMA_D = 1 };           /* resistivity law */
+
+/* Problem description.  Field order is part of the ABI. */
+typedef struct gr_grid {
+    int ndim;             /* 1..3; active directions are x, then y, then z      */
+    int n[3];             /* interior cells per direction (1 when inactive)     */
+    int ng;               /* ghost width: >= 2 (minmod, MC), >= 3 (PPM)         */
+    double lo[3], hi[3];  /* domain                                            */
+    int bc[3][2];         /* GR_OUTFLOW / GR_PERIODIC / GR_FIXED per side       */
+    double gamma_ad;      /* ideal gas p = (Gamma - 1) rho eps                  */
+    int recon;            /* GR_MINMOD / GR_MC / GR_PPM                         */
+    int imex;             /* GR_SSP2_222 / GR_SSP3_433                          */
+    double cfl;           /* dt = cfl / max sum_d alpha sqrt(gamma^dd) / dx_d   */
+    int eta_mode;         /* GR_ETA_UNIFORM: eta; GR_ETA_SIGMA_D: eq. sigma_D    */
+    double eta, sigma0, eta_min, eta_max;
+    double rho_atm, p_atm;/* atmosphere state                                  */
+    int metric;           /* 0 flat, 1 static conformally flat (alpha, psi)     */
+    double newton_tol;    /* Newton stop: |du~|_inf <= tol (1 + |u~|_inf)       */
+    int newton_maxit;
+    double xi;            /* mean-field dynamo; must be 0                       */
+    double atm_factor;    /* cells with D <= atm_factor rho_atm are atmosphere  */
+} gr_grid;
+
+/* Device state of one run (all pointers caller-owned device memory). */
+typedef struct gr_state {
+    double *q;            /* 8-field block                                     */
+    double *face;         /* 3-field block                                     */
+    double *prim;         /* 5-field block                                     */
+    double *metric;       /* 2-field block or NULL when grid->metric == 0       */
+    void *work;           /* workspace of gr_workspace_bytes(grid) bytes        */
+    size_t work_bytes;
+} gr_state;
+
+int gr_abi_version(void);
+const char *gr_strerror(gr_status s);
+
+/* Checks a grid description; GR_OK when every other call accepts it. */
+gr_status gr_validate(const gr_grid *grid);
+
+/* Doubles between consecutive fields of a field block. */
+size_t gr_field_stride(const gr_grid *grid);
+
+/* Bytes of workspace the stage calls need (stage states, stored L and R
+ * terms of the IMEX tableau, scratch, counters). */
+size_t gr_workspace_bytes(const gr_grid *grid);
+
+/* Byte offset inside the workspace of one field of stage storage, for
+ * inspection: kind 0 = stage primitives + E (8 fields: rho, u~, p, E^i),
+ * 1 = stage face fields (3), 2 = stored L (11: 8 cell + 3 face), 3 = stored
+ * R (3, q_E rows).  stage is 0-based (< number of implicit stages). */
+gr_status gr_workspace_offset(const gr_grid *grid, int kind, int stage, int field, size_t *offset_bytes);
+
+/* Initial state (Sec 4 and Sec 2.1): face fields q_B^i = eta^{ijk} d_j A_k
+ * from the edge vector potential A_host (3 edge arrays back to back, or
+ * NULL), plus face_host (3 cell-sized arrays, densitised, or NULL); q_E =
+ * psi^6 E everywhere; D, S, tau from the primitives on interior cells.
+ * prim_host: 5 cell arrays, E_host: 3 cell arrays, metric_host: 2 cell arrays
+ * (alpha, psi) or NULL; all with the cell-array layout above (contiguous,
+ * stride Nx Ny Nz between fields).  Also resets the failure counter and fills
+ * the ghost points of the workspace stage storage.  Synchronises the stream. */
+gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim_host, const double *E_host,
+                        const double *A_host, const double *face_host, const double *metric_host,
+                        hipStream_t stream);
+
+/* One pass of the IMEX-RK step (Sec 2.3): pass p = 0 .. s-1 is implicit
+ * stage p+1 (it first evaluates the explicit operator L of stage p when the
+ * tableau needs it, then accumulates q* and solves the stiff Ohm's-law
+ * update fused with the primitive recovery, Sec 2.4); pass p = s is the
+ * final combination followed by the recovery with E and B known (Sec 2.6).
+ * s = 2 for GR_SSP2_222, 4 for GR_SSP3_433.  Passes must run in order. */
+gr_status gr_imex_stage(const gr_grid *grid, gr_state *state, int pass, double dt, hipStream_t stream);
+
+/* All passes of one step. */
+gr_status gr_step(const gr_grid *grid, gr_state *state, double dt, hipStream_t stream);
+
+/* Primitive recovery with E and B known (Sec 2.6) on the interior cells of
+ * the state; atmosphere and failure rules as in the step. */
+gr_status gr_con2prim(const gr_grid *grid, gr_state *state, hipStream_t stream);
+
+/* Discrete divergence of the face field on interior cells,
+ * div = sum_d (q_B^d(+1/2) - q_B^d(-1/2)) / dx_d (Sec 3, eq. divb_0):
+ * out3_dev[0] = mean |div|, [1] = sqrt(mean div^2), [2] = max |div|.
+ * Uses the workspace scratch; deterministic reduction order. */
+gr_status gr_divB_norm(const gr_grid *grid, const gr_state *state, double *out3_dev, hipStream_t stream);
+
+/* Time step of Sec 2.5 (maximum-diffusivity speeds depend on the metric
+ * only).  Synchronises the stream; result written to *dt_host. */
+gr_status gr_cfl_dt(const gr_grid *grid, const gr_state *state, double *dt_host, hipStream_t stream);
+
+/* Cells that fell back to the atmosphere after a failed or unphysical
+ * recovery since gr_init_state.  Synchronises the stream. */
+gr_status gr_fail_count(const gr_grid *grid, const gr_state *state, unsigned long long *count_host,
+                        hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

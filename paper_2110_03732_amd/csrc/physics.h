@@ -1,0 +1,285 @@
+// physics.h -- point-wise FP64 device physics of resistive GRMHD for gfx950.
+//
+// Every local operation is written in the orthonormal frame of the static
+// conformally flat metric gamma_ij = psi^4 delta_ij: with u = psi^2 u~,
+// E = psi^2 E^i, B = psi^2 B^i and S = S_i / psi^2, the conserved variables,
+// fluxes, the implicit Ohm's-law update and the primitive recovery take their
+// special-relativistic (flat) form; the metric re-enters only through scale
+// factors applied by the callers.  Reference: Cheong et al.,
+// arXiv:2110.03732, Sec 2.1 (conserved variables and fluxes), Sec 2.4
+// (implicit step), Sec 2.6 (recovery with E, B known).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gr {
+
+struct Phys {
+    double gam;      // adiabatic index Gamma
+    double G1;       // Gamma / (Gamma - 1)
+    double rho_atm, p_atm, D_atm;  // atmosphere state, D threshold
+    double tol;      // Newton tolerance
+    int maxit;
+    int eta_mode;
+    double eta, sigma0, eta_min, eta_max;
+};
+
+__device__ __forceinline__ double sq(double x) { return x * x; }
+
+// flat-frame primitive state -> conserved (D, S_x..z, tau) and the flux in
+// direction d (f_D, f_S, f_tau, f_E); Sec 2.1 with alpha = psi = 1
+struct Cons { double D, S[3], tau; };
+
+__device__ __forceinline__ void flat_cons_flux(const Phys &P, int d, double rho, const double u[3], double p,
+                                               const double E[3], const double B[3], double q[8], double f[8])
+{
+    double W = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    double iW = 1.0 / W;
+    double v[3] = {u[0] * iW, u[1] * iW, u[2] * iW};
+    double rhoh = rho + P.G1 * p;
+    double w = rhoh * W * W;   // rho h W^2
+    double E2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
+    double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+    double U = 0.5 * (E2 + B2);
+    double ExB[3] = {E[1] * B[2] - E[2] * B[1], E[2] * B[0] - E[0] * B[2], E[0] * B[1] - E[1] * B[0]};
+    double D = rho * W;
+    double S[3] = {w * v[0] + ExB[0], w * v[1] + ExB[1], w * v[2] + ExB[2]};
+    double tau = w - p + U - D;
+    q[0] = D;
+    q[1] = S[0];
+    q[2] = S[1];
+    q[3] = S[2];
+    q[4] = tau;
+    q[5] = E[0];
+    q[6] = E[1];
+    q[7] = E[2];
+    double vd = v[d];
+    f[0] = D * vd;
+    double pt = p + U;
+#pragma unroll
+    for (int j = 0; j < 3; j++) f[1 + j] = w * vd * v[j] - E[d] * E[j] - B[d] * B[j] + (j == d ? pt : 0.0);
+    f[4] = S[d] - vd * D;
+    // f_E^j = eta^{d j k} B^k
+    int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    f[5 + d] = 0.0;
+    f[5 + d1] = B[d2];
+    f[5 + d2] = -B[d1];
+}
+
+// resistivity of a cell: uniform, or 1/sigma_c of eq. sigma_D clamped to
+// [eta_min, eta_max], with D_atmo the atmosphere threshold D_atm
+__device__ __forceinline__ double cell_eta(const Phys &P, double Dund)
+{
+    if (P.eta_mode == 0) return P.eta;
+    double x = 1.0 - P.D_atm / Dund;
+    x = x < 0.0 ? 0.0 : x;
+    double sig = P.sigma0 * x * x;
+    if (sig * P.eta_max <= 1.0) return P.eta_max;
+    double e = 1.0 / sig;
+    return e < P.eta_min ? P.eta_min : e;
+}
+
+// Fused implicit E update + velocity recovery (Sec 2.4, xi = 0), flat frame.
+// E(u) = [et E* + A1 (E*.u) u - u x B] / A0, A0 = W + et, A1 = et/(1 + et W);
+// f(u) = w~ u - (S - E x B), w~ = [W (tau + D - U) - D/G1]/(W^2 - 1/G1).
+// Newton with the analytic Jacobian, 3x3 solve by the adjugate, backtracking
+// line search on F = f.f/2 (Armijo 1e-4, quadratic model, cut in [0.1, 0.5]).
+// Returns 0 converged, 1 not converged.  u (in: guess, out: root), E, wt.
+struct ImpSys {
+    double D, tau, S[3], Es[3], B[3], et, G1;
+};
+
+__device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], double f[3], double E[3], double &wt,
+                                         double &W)
+{
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    W = sqrt(1.0 + uu);
+    double A0 = W + s.et, A1 = s.et / (1.0 + s.et * W);
+    double Esu = s.Es[0] * u[0] + s.Es[1] * u[1] + s.Es[2] * u[2];
+    double uxB[3] = {u[1] * s.B[2] - u[2] * s.B[1], u[2] * s.B[0] - u[0] * s.B[2], u[0] * s.B[1] - u[1] * s.B[0]};
+    double iA0 = 1.0 / A0;
+#pragma unroll
+    for (int i = 0; i < 3; i++) E[i] = (s.et * s.Es[i] + A1 * Esu * u[i] - uxB[i]) * iA0;
+    double U = 0.5 * (E[0] * E[0] + E[1] * E[1] + E[2] * E[2] + s.B[0] * s.B[0] + s.B[1] * s.B[1] + s.B[2] * s.B[2]);
+    double den = W * W - 1.0 / s.G1;
+    wt = (W * (s.tau + s.D - U) - s.D / s.G1) / den;
+    double ExB[3] = {E[1] * s.B[2] - E[2] * s.B[1], E[2] * s.B[0] - E[0] * s.B[2], E[0] * s.B[1] - E[1] * s.B[0]};
+#pragma unroll
+    for (int i = 0; i < 3; i++) f[i] = wt * u[i] - (s.S[i] - ExB[i]);
+}
+
+__device__ __forceinline__ void imp_jac(const ImpSys &s, const double u[3], const double E[3], double wt, double W,
+                                        double J[3][3])
+{
+    double et = s.et;
+    double A0 = W + et, opW = 1.0 + et * W, A1 = et / opW, A1d = -et * et / (opW * opW);
+    double Esu = s.Es[0] * u[0] + s.Es[1] * u[1] + s.Es[2] * u[2];
+    double iA0W = 1.0 / (A0 * W);
+    double dE[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            double t = -E[i] * u[j] + A1 * W * u[i] * s.Es[j] + (A1 * W * (i == j ? 1.0 : 0.0) + A1d * u[i] * u[j]) * Esu;
+            // - W eps_{i j m} B_m
+            int m = 3 - i - j;
+            if (i != j) {
+                double e = ((j - i + 3) % 3 == 1) ? 1.0 : -1.0;
+                t -= W * e * s.B[m];
+            }
+            dE[i][j] = t * iA0W;
+        }
+    double U = 0.5 * (E[0] * E[0] + E[1] * E[1] + E[2] * E[2] + s.B[0] * s.B[0] + s.B[1] * s.B[1] + s.B[2] * s.B[2]);
+    double den = W * W - 1.0 / s.G1;
+    double tDU = s.tau + s.D - U;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        double dU = E[0] * dE[0][j] + E[1] * dE[1][j] + E[2] * dE[2][j];
+        double dw = (tDU * u[j] / W - 2.0 * wt * u[j] - W * dU) / den;
+        // d(E x B)_i/du_j = eps_{ilm} dE_l/du_j B_m
+        double dxB0 = dE[1][j] * s.B[2] - dE[2][j] * s.B[1];
+        double dxB1 = dE[2][j] * s.B[0] - dE[0][j] * s.B[2];
+        double dxB2 = dE[0][j] * s.B[1] - dE[1][j] * s.B[0];
+        J[0][j] = (j == 0 ? wt : 0.0) + u[0] * dw + dxB0;
+        J[1][j] = (j == 1 ? wt : 0.0) + u[1] * dw + dxB1;
+        J[2][j] = (j == 2 ? wt : 0.0) + u[2] * dw + dxB2;
+    }
+}
+
+__device__ __forceinline__ bool solve3(const double J[3][3], const double b[3], double x[3])
+{
+    double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    if (!(det != 0.0) || !isfinite(det)) return false;
+    double id = 1.0 / det;
+    double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    x[0] = (c00 * b[0] + c10 * b[1] + c20 * b[2]) * id;
+    x[1] = (c01 * b[0] + c11 * b[1] + c21 * b[2]) * id;
+    x[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
+    return true;
+}
+
+__device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int maxit, double u[3], double E[3],
+                                              double &wt, double &W)
+{
+    double f[3], J[3][3];
+    imp_eval(s, u, f, E, wt, W);
+    double F = 0.5 * (f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (int it = 0; it < maxit; it++) {
+        imp_jac(s, u, E, wt, W, J);
+        double mf[3] = {-f[0], -f[1], -f[2]}, dx[3];
+        if (!solve3(J, mf, dx)) return 1;
+        double dmax = fmax(fabs(dx[0]), fmax(fabs(dx[1]), fabs(dx[2])));
+        double umax = fmax(fabs(u[0]), fmax(fabs(u[1]), fabs(u[2])));
+        if (dmax <= tol * (1.0 + umax)) {
+            u[0] += dx[0];
+            u[1] += dx[1];
+            u[2] += dx[2];
+            imp_eval(s, u, f, E, wt, W);
+            return 0;
+        }
+        double slope = -2.0 * F, lam = 1.0, un[3], fn[3], En[3], wn, Wn, Fn = 0.0;
+        bool ok = false;
+        for (int ls = 0; ls < 60; ls++) {
+            un[0] = u[0] + lam * dx[0];
+            un[1] = u[1] + lam * dx[1];
+            un[2] = u[2] + lam * dx[2];
+            imp_eval(s, un, fn, En, wn, Wn);
+            Fn = 0.5 * (fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]);
+            if (isfinite(Fn) && Fn <= F + 1e-4 * lam * slope) {
+                ok = true;
+                break;
+            }
+            double lnew = isfinite(Fn) ? -slope * lam * lam / (2.0 * (Fn - F - slope * lam)) : 0.1 * lam;
+            if (!(lnew >= 0.1 * lam)) lnew = 0.1 * lam;
+            if (lnew > 0.5 * lam) lnew = 0.5 * lam;
+            lam = lnew;
+        }
+        if (!ok) return 1;
+        u[0] = un[0];
+        u[1] = un[1];
+        u[2] = un[2];
+        f[0] = fn[0];
+        f[1] = fn[1];
+        f[2] = fn[2];
+        E[0] = En[0];
+        E[1] = En[1];
+        E[2] = En[2];
+        wt = wn;
+        W = Wn;
+        F = Fn;
+    }
+    return 1;
+}
+
+// Recovery with E and B known (Sec 2.6), flat frame: the root in p of
+// g(p) = (Gamma-1) rho eps(p) - p with v = S_f/(tau_f + D + p), rho = D/W,
+// rho eps = [tau_f + D (1 - W) + p (1 - W^2)]/W^2, by Newton steps kept inside
+// a shrinking sign bracket (bisection when a step leaves it).
+// Returns 0 ok (p, W, Z = tau_f + D + p), 1 no physical root.
+__device__ __forceinline__ double c2p_g(double gm1, double p, double D, double tauf, double Sf2, double &dg,
+                                        double &W)
+{
+    double Z = tauf + D + p;
+    double iZ = 1.0 / Z;
+    double v2 = Sf2 * iZ * iZ;
+    if (!(v2 < 1.0)) {
+        dg = 0.0;
+        W = INFINITY;
+        return -INFINITY;
+    }
+    double iW2 = 1.0 - v2;
+    double iW = sqrt(iW2);
+    W = 1.0 / iW;
+    double rhoeps = (tauf + D) * iW2 - D * iW + p * (iW2 - 1.0);
+    double a = 2.0 * Sf2 * iZ * iZ * iZ;  // d(1/W^2)/dp
+    double drhoeps = (tauf + D) * a - D * W * 0.5 * a + (iW2 - 1.0) + p * a;
+    dg = gm1 * drhoeps - 1.0;
+    return gm1 * rhoeps - p;
+}
+
+__device__ __forceinline__ int c2p_pressure(double gm1, double D, double tauf, double Sf2, double pguess, double &p,
+                                            double &W)
+{
+    if (!(D > 0.0)) return 1;
+    double lo = sqrt(Sf2) - tauf - D;
+    lo = lo < 0.0 ? 0.0 : lo;
+    double hi = lo + 2.0 * gm1 * fabs(tauf) + 1e-300;
+    double dg, Wt;
+    if (c2p_g(gm1, hi, D, tauf, Sf2, dg, Wt) > 0.0) return 1;
+    if (lo == 0.0) {
+        double g0 = c2p_g(gm1, 0.0, D, tauf, Sf2, dg, Wt);
+        if (g0 < 0.0) return 1;
+        if (g0 == 0.0) {
+            p = 0.0;
+            W = Wt;
+            return 0;
+        }
+    }
+    double x = pguess;
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; it++) {
+        double g = c2p_g(gm1, x, D, tauf, Sf2, dg, Wt);
+        if (g > 0.0) lo = x;
+        else hi = x;
+        double xn = x - g / dg;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        double dx = fabs(xn - x);
+        x = xn;
+        if (dx <= 1e-15 * x || hi - lo <= 1e-15 * hi) break;
+    }
+    p = x;
+    double Z = tauf + D + p;
+    double v2 = Sf2 / (Z * Z);
+    if (!(v2 < 1.0)) return 1;
+    W = 1.0 / sqrt(1.0 - v2);
+    return 0;
+}
+
+}  // namespace gr

@@ -1,0 +1,263 @@
+"""Thin ctypes binding of the C ABI in include/grmhd.h (libgrmhd.so).
+
+Function names are those of the C ABI.  PyTorch is used only for device
+memory and streams: every step of the method runs in the library's HIP
+kernels.  Loading fails loudly when the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrmhd.so")
+
+GR_OK, GR_EINVAL, GR_ENOMEM, GR_EHIP, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
+EXPORTED = ["gr_abi_version", "gr_strerror", "gr_validate", "gr_field_stride", "gr_workspace_bytes",
+            "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim", "gr_divB_norm",
+            "gr_cfl_dt", "gr_fail_count"]
+
+
+class GrError(RuntimeError):
+    pass
+
+
+class gr_grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("ng", ctypes.c_int),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3), ("bc", (ctypes.c_int * 2) * 3),
+                ("gamma_ad", ctypes.c_double), ("recon", ctypes.c_int), ("imex", ctypes.c_int),
+                ("cfl", ctypes.c_double), ("eta_mode", ctypes.c_int), ("eta", ctypes.c_double),
+                ("sigma0", ctypes.c_double), ("eta_min", ctypes.c_double), ("eta_max", ctypes.c_double),
+                ("rho_atm", ctypes.c_double), ("p_atm", ctypes.c_double), ("metric", ctypes.c_int),
+                ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int), ("xi", ctypes.c_double),
+                ("atm_factor", ctypes.c_double)]
+
+
+class gr_state(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_void_p), ("face", ctypes.c_void_p), ("prim", ctypes.c_void_p),
+                ("metric", ctypes.c_void_p), ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GrError("libgrmhd.so is not built (run __graft_entry__.build()): %s" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        G = ctypes.POINTER(gr_grid)
+        S = ctypes.POINTER(gr_state)
+        V = ctypes.c_void_p
+        D = ctypes.POINTER(ctypes.c_double)
+        L.gr_abi_version.restype = ctypes.c_int
+        L.gr_strerror.restype = ctypes.c_char_p
+        L.gr_strerror.argtypes = [ctypes.c_int]
+        L.gr_validate.argtypes = [G]
+        L.gr_field_stride.argtypes = [G]
+        L.gr_field_stride.restype = ctypes.c_size_t
+        L.gr_workspace_bytes.argtypes = [G]
+        L.gr_workspace_bytes.restype = ctypes.c_size_t
+        L.gr_workspace_offset.argtypes = [G, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.gr_init_state.argtypes = [G, S, D, D, D, D, D, V]
+        L.gr_imex_stage.argtypes = [G, S, ctypes.c_int, ctypes.c_double, V]
+        L.gr_step.argtypes = [G, S, ctypes.c_double, V]
+        L.gr_con2prim.argtypes = [G, S, V]
+        L.gr_divB_norm.argtypes = [G, S, V, V]
+        L.gr_cfl_dt.argtypes = [G, S, D, V]
+        L.gr_fail_count.argtypes = [G, S, ctypes.POINTER(ctypes.c_ulonglong), V]
+        for name in ("gr_validate", "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim",
+                     "gr_divB_norm", "gr_cfl_dt", "gr_fail_count"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _chk(r):
+    if r != GR_OK:
+        raise GrError("libgrmhd: %s (%d)" % (lib().gr_strerror(r).decode(), r))
+
+
+# ---------------------------------------------------------------------------
+# C-ABI wrappers (same names); argument marshalling only
+def gr_abi_version():
+    return lib().gr_abi_version()
+
+
+def gr_validate(grid):
+    return lib().gr_validate(ctypes.byref(grid))
+
+
+def gr_field_stride(grid):
+    return lib().gr_field_stride(ctypes.byref(grid))
+
+
+def gr_workspace_bytes(grid):
+    return lib().gr_workspace_bytes(ctypes.byref(grid))
+
+
+def gr_workspace_offset(grid, kind, stage, field):
+    off = ctypes.c_size_t(0)
+    _chk(lib().gr_workspace_offset(ctypes.byref(grid), kind, stage, field, ctypes.byref(off)))
+    return off.value
+
+
+def _hp(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def gr_init_state(grid, state, prim_host, E_host, A_host, face_host, metric_host, stream):
+    _chk(lib().gr_init_state(ctypes.byref(grid), ctypes.byref(state), _hp(prim_host), _hp(E_host), _hp(A_host),
+                             _hp(face_host), _hp(metric_host), ctypes.c_void_p(stream)))
+
+
+def gr_imex_stage(grid, state, p, dt, stream):
+    _chk(lib().gr_imex_stage(ctypes.byref(grid), ctypes.byref(state), p, dt, ctypes.c_void_p(stream)))
+
+
+def gr_step(grid, state, dt, stream):
+    _chk(lib().gr_step(ctypes.byref(grid), ctypes.byref(state), dt, ctypes.c_void_p(stream)))
+
+
+def gr_con2prim(grid, state, stream):
+    _chk(lib().gr_con2prim(ctypes.byref(grid), ctypes.byref(state), ctypes.c_void_p(stream)))
+
+
+def gr_divB_norm(grid, state, out3_dev_ptr, stream):
+    _chk(lib().gr_divB_norm(ctypes.byref(grid), ctypes.byref(state), ctypes.c_void_p(out3_dev_ptr),
+                            ctypes.c_void_p(stream)))
+
+
+def gr_cfl_dt(grid, state, stream):
+    dt = ctypes.c_double(0.0)
+    _chk(lib().gr_cfl_dt(ctypes.byref(grid), ctypes.byref(state), ctypes.byref(dt), ctypes.c_void_p(stream)))
+    return dt.value
+
+
+def gr_fail_count(grid, state, stream):
+    c = ctypes.c_ulonglong(0)
+    _chk(lib().gr_fail_count(ctypes.byref(grid), ctypes.byref(state), ctypes.byref(c), ctypes.c_void_p(stream)))
+    return c.value
+
+
+# ---------------------------------------------------------------------------
+def grid_of(s) -> gr_grid:
+    """gr_grid of a workloads.Setup"""
+    g = gr_grid()
+    g.ndim = s.ndim
+    for d in range(3):
+        g.n[d] = s.nn(d)
+        g.lo[d] = s.lo[d]
+        g.hi[d] = s.hi[d]
+        g.bc[d][0] = s.bc[d][0]
+        g.bc[d][1] = s.bc[d][1]
+    g.ng = s.ng
+    g.gamma_ad = s.gamma_ad
+    g.recon = s.recon
+    g.imex = s.imex
+    g.cfl = s.cfl
+    g.eta_mode = s.eta_mode
+    g.eta = s.eta
+    g.sigma0 = s.sigma0
+    g.eta_min = s.eta_min
+    g.eta_max = s.eta_max
+    g.rho_atm = s.rho_atm
+    g.p_atm = s.p_atm
+    g.metric = s.metric
+    g.newton_tol = s.newton_tol
+    g.newton_maxit = s.newton_maxit
+    g.xi = s.xi
+    g.atm_factor = s.atm_factor
+    return g
+
+
+class Run:
+    """Device state of one run: torch tensors for the field blocks and the
+    workspace, and the gr_grid / gr_state structs that point at them."""
+
+    def __init__(self, setup, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.setup = setup
+        self.grid = grid_of(setup)
+        r = gr_validate(self.grid)
+        _chk(r)
+        self.fs = gr_field_stride(self.grid)
+        self.np = int(np.prod(setup.shape))
+        dev = torch.device(device)
+        self.q = torch.zeros(8 * self.fs, dtype=torch.float64, device=dev)
+        self.face = torch.zeros(3 * self.fs, dtype=torch.float64, device=dev)
+        self.prim = torch.zeros(5 * self.fs, dtype=torch.float64, device=dev)
+        self.metric = torch.zeros(2 * self.fs, dtype=torch.float64, device=dev) if setup.metric else None
+        wb = gr_workspace_bytes(self.grid)
+        self.work = torch.zeros((wb + 7) // 8, dtype=torch.float64, device=dev)
+        self.state = gr_state()
+        self.state.q = self.q.data_ptr()
+        self.state.face = self.face.data_ptr()
+        self.state.prim = self.prim.data_ptr()
+        self.state.metric = self.metric.data_ptr() if self.metric is not None else None
+        self.state.work = self.work.data_ptr()
+        self.state.work_bytes = wb
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        s = setup
+        prim = np.ascontiguousarray(s.prim.reshape(5, -1))
+        E = np.ascontiguousarray(s.E.reshape(3, -1))
+        A = np.ascontiguousarray(s.A.reshape(3, -1)) if s.A is not None else None
+        face = np.ascontiguousarray(s.face.reshape(3, -1)) if s.face is not None else None
+        met = np.ascontiguousarray(np.stack([s.alpha, s.psi]).reshape(2, -1)) if s.metric else None
+        gr_init_state(self.grid, self.state, prim, E, A, face, met, self.stream.cuda_stream)
+        self.t = 0.0
+
+    # --- stepping ---------------------------------------------------------
+    def dt(self):
+        return gr_cfl_dt(self.grid, self.state, self.stream.cuda_stream)
+
+    def step(self, dt):
+        gr_step(self.grid, self.state, dt, self.stream.cuda_stream)
+        self.t += dt
+
+    def stage(self, p, dt):
+        gr_imex_stage(self.grid, self.state, p, dt, self.stream.cuda_stream)
+
+    def con2prim(self):
+        gr_con2prim(self.grid, self.state, self.stream.cuda_stream)
+
+    def divB(self):
+        out = self.torch.zeros(3, dtype=self.torch.float64, device=self.q.device)
+        gr_divB_norm(self.grid, self.state, out.data_ptr(), self.stream.cuda_stream)
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def fail_count(self):
+        return gr_fail_count(self.grid, self.state, self.stream.cuda_stream)
+
+    # --- views (host copies) ------------------------------------------------
+    def _block(self, t, nf):
+        self.stream.synchronize()
+        a = t.view(nf, self.fs)[:, : self.np].cpu().numpy()
+        return a.reshape((nf,) + self.setup.shape)
+
+    def prims(self):
+        return self._block(self.prim, 5)
+
+    def cons(self):
+        return self._block(self.q, 8)
+
+    def faces(self):
+        return self._block(self.face, 3)
+
+    def E(self):
+        q = self.cons()
+        ps6 = 1.0 if not self.setup.metric else self.setup.psi ** 6
+        return q[5:8] / ps6
+
+    def work_field(self, kind, stage, field):
+        off = gr_workspace_offset(self.grid, kind, stage, field) // 8
+        self.stream.synchronize()
+        return self.work[off: off + self.np].cpu().numpy().reshape(self.setup.shape)

@@ -1,0 +1,77 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-side
+logic (validation, layout) behaves; no device calls (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workloads as W
+from paper_2110_03732_amd import grmhd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "grmhd.h")).read()
+    return sorted(set(re.findall(r"\b(gr_[a-zA-Z0-9_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == sorted(grmhd.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = grmhd.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    assert grmhd.gr_abi_version() == 1
+
+
+def test_validation_rejects_bad_grids():
+    s = W.blast_wave(16)
+    g = grmhd.grid_of(s)
+    assert grmhd.gr_validate(g) == 0
+    for field, bad in [("ndim", 4), ("ng", 2), ("recon", 7), ("imex", 3), ("gamma_ad", 1.0), ("newton_maxit", 0),
+                       ("rho_atm", 0.0), ("atm_factor", 0.5)]:
+        g2 = grmhd.grid_of(s)
+        setattr(g2, field, bad)
+        assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL, field
+    g2 = grmhd.grid_of(s)
+    g2.xi = 0.1
+    assert grmhd.gr_validate(g2) == grmhd.GR_EUNSUPPORTED
+    g2 = grmhd.grid_of(s)
+    g2.bc[0][0] = W.PERIODIC  # periodic on one side only
+    assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
+    g2 = grmhd.grid_of(s)
+    g2.n[0] = 2
+    g2.bc[0][0] = g2.bc[0][1] = W.PERIODIC  # fewer cells than ghosts
+    assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
+    assert grmhd.gr_workspace_bytes(g2) == 0
+
+
+@pytest.mark.parametrize("make", [lambda: W.shock_tube(400), lambda: W.blast_wave(512), lambda: W.tov_star(32)])
+def test_layout(make):
+    s = make()
+    g = grmhd.grid_of(s)
+    fs = grmhd.gr_field_stride(g)
+    assert fs >= s.shape[0] * s.shape[1] * s.shape[2] and fs % 32 == 0
+    wb = grmhd.gr_workspace_bytes(g)
+    nst = 2 if s.imex == W.SSP2 else 4
+    offs = set()
+    for kind, nf in [(0, 8), (1, 3), (2, 11), (3, 3)]:
+        for st in range(nst):
+            for f in range(nf):
+                o = grmhd.gr_workspace_offset(g, kind, st, f)
+                assert o % 256 == 0 and o + 8 * fs <= wb
+                offs.add(o)
+    assert len(offs) == nst * 25  # no two fields share storage
+    with pytest.raises(grmhd.GrError):
+        grmhd.gr_workspace_offset(g, 0, nst, 0)
+
+
+def test_strerror():
+    L = grmhd.lib()
+    assert L.gr_strerror(0) == b"ok"
+    assert L.gr_strerror(-2) == b"workspace too small"
+    assert ctypes.sizeof(grmhd.gr_grid) > 0
