@@ -146,6 +146,22 @@ gr_status gr_cfl_dt(const gr_grid *grid, const gr_state *state, double *dt_host,
 gr_status gr_fail_count(const gr_grid *grid, const gr_state *state, unsigned long long *count_host,
                         hipStream_t stream);
 
+/* Measurement hook (not part of the method): while the bit of a kernel
+ * class is set in kernel_class_mask, every launch of that class is
+ * bracketed by two HIP events recorded on the stream it is launched on,
+ * together with the algorithmic bytes of the launch (each live input field
+ * read once, each output field written once).  gr_timing_start clears
+ * earlier records; mask 0 switches recording off.  Host-side state shared by
+ * all calls of the process. */
+gr_status gr_timing_start(unsigned kernel_class_mask);
+
+/* Totals of the records of one kernel class: summed event time (ms), number
+ * of launches, summed algorithmic bytes.  Waits for the recorded events. */
+gr_status gr_timing_read(int kernel_class, double *total_ms, long *launches, double *alg_bytes);
+
+/* Name of a kernel class ("" when out of range). */
+const char *gr_kernel_class_name(int kernel_class);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "../../include/grmhd.h"
 #include "physics.h"
@@ -115,6 +117,43 @@ __device__ __forceinline__ long lin(const Geo &G, const int c[3]) { return c[0] 
 struct Region {
     int lo[3], cnt[3];
     long total;
+};
+
+// ---------------------------------------------------------------------------
+// measurement hook: launches of the selected kernel classes are bracketed by
+// HIP events on the stream they are launched on, with the algorithmic bytes
+// (every live input field read once, every output written once) of the launch
+enum KClass { KC_FACE_FLUX = 0, KC_FACE_E, KC_EDGE_EMF, KC_FACE_UPDATE, KC_CELL_UPDATE, KC_GHOST, KC_COUNT };
+struct TRec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+};
+std::mutex g_tmu;
+unsigned g_tmask = 0;
+std::vector<TRec> g_trecs;
+
+struct TScope {
+    int cls;
+    hipStream_t s;
+    double bytes;
+    hipEvent_t a = nullptr;
+    TScope(int c, hipStream_t st, double b) : cls(c), s(st), bytes(b)
+    {
+        if (g_tmask & (1u << c)) {
+            if (hipEventCreate(&a) == hipSuccess) hipEventRecord(a, s);
+            else a = nullptr;
+        }
+    }
+    ~TScope()
+    {
+        if (!a) return;
+        hipEvent_t b;
+        if (hipEventCreate(&b) != hipSuccess) return;
+        hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_tmu);
+        g_trecs.push_back({cls, a, b, bytes});
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -976,9 +1015,12 @@ gr_status launch_L(const gr_grid *g, const Geo &G, const Phys &P, gr_state *st, 
                    hipStream_t s, double *F, double *Ef, double *EM)
 {
     const double *met = st->metric;
+    const int r = (REC == GR_PPM) ? 3 : 2;
     for (int d = 0; d < 3; d++) {
         if (!G.act[d]) continue;
         Region R = region(G, 1 << d);
+        double cells = (double)R.total / R.cnt[d] * (G.n[d] + 2 * r);
+        TScope ts(KC_FACE_FLUX, s, 8.0 * (cells * (8 + 2 + 2 * MET) + R.total * (1 + 8)));
         hipLaunchKernelGGL((k_face_flux<REC, MET>), dim3(nblocks(R.total)), dim3(kBlock), 0, s, G, P, d, R, sp, sf,
                            met, F + (size_t)d * 8 * G.fs);
         LAUNCHCHK();
@@ -988,10 +1030,14 @@ gr_status launch_L(const gr_grid *g, const Geo &G, const Phys &P, gr_state *st, 
         if (!G.act[a] && !G.act[b]) continue;
         Region Rf = region(G, 1 << a, 1 << b);
         double *EfL = Ef + (size_t)(2 * k) * G.fs, *EfR = Ef + (size_t)(2 * k + 1) * G.fs;
-        hipLaunchKernelGGL((k_face_E<REC, MET>), dim3(nblocks(Rf.total)), dim3(kBlock), 0, s, G, k, Rf, sp, met, EfL,
-                           EfR);
-        LAUNCHCHK();
+        {
+            TScope ts(KC_FACE_E, s, 8.0 * Rf.total * (1 + 2 * MET + 2));
+            hipLaunchKernelGGL((k_face_E<REC, MET>), dim3(nblocks(Rf.total)), dim3(kBlock), 0, s, G, k, Rf, sp, met,
+                               EfL, EfR);
+            LAUNCHCHK();
+        }
         Region Re = region(G, (1 << a) | (1 << b));
+        TScope ts(KC_EDGE_EMF, s, 8.0 * (2.0 * Rf.total + Re.total * (2 + 2 * MET + 1)));
         hipLaunchKernelGGL((k_edge_emf<REC, MET>), dim3(nblocks(Re.total)), dim3(kBlock), 0, s, G, k, Re, sf, met,
                            EfL, EfR, EM + (size_t)k * G.fs);
         LAUNCHCHK();
@@ -1007,6 +1053,7 @@ gr_status ghost_fill(const gr_grid *g, const Geo &G, double *cells, double *face
             int bc = g->bc[d][side];
             if (bc == GR_FIXED) continue;
             long total = (long)G.N[(d + 1) % 3] * G.N[(d + 2) % 3] * G.g[d];
+            TScope ts(KC_GHOST, s, 8.0 * total * 11 * 2);
             hipLaunchKernelGGL(k_ghost, dim3(nblocks(total)), dim3(kBlock), 0, s, G, d, side, bc, cells, faces);
             LAUNCHCHK();
         }
@@ -1049,8 +1096,14 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
     }
     // faces of this pass
     double *fout = fin ? st->face : wfield(st, G, Ly.sface + 3 * (size_t)p);
+    int nLst = 0, nRst = 0;
+    for (int j = 0; j < p && j < 4; j++) {
+        if (A.cL[j] != 0.0 && !(withL && j == p - 1)) nLst++;
+        if (A.cR[j] != 0.0) nRst++;
+    }
     for (int d = 0; d < 3; d++) {
         Region R = region(G, 1 << d);
+        TScope ts(KC_FACE_UPDATE, s, 8.0 * R.total * (2 * (int)withL + 1 + nLst + 1 + (int)withL));
         hipLaunchKernelGGL(k_face_update, dim3(nblocks(R.total)), dim3(kBlock), 0, s, G, d, R, A, EM, st->face, Lall,
                            fout);
         LAUNCHCHK();
@@ -1059,6 +1112,11 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
     Region Rc = region(G, 0);
     double *out = fin ? st->prim : wfield(st, G, Ly.sprim + 8 * (size_t)p);
     const double *guess = (p == 0 || fin) ? st->prim : sp_prev;
+    double cb = 8 + 3 + 2 * MET + 8 * nLst + 3 * nRst + (fin ? 1 : 3);           // q, faces, metric, L, R, guess
+    if (withL) cb += 3 * 8 + 8 + 3;                                              // fluxes, stage p-1 prims/E, faces
+    cb += fin ? (8 + 5) : (8 + 3);                                               // outputs
+    if (withL) cb += 8;                                                          // stored L
+    TScope ts(KC_CELL_UPDATE, s, 8.0 * Rc.total * cb);
     hipLaunchKernelGGL((k_cell_update<MET>), dim3(nblocks(Rc.total)), dim3(kBlock), 0, s, G, P, Rc, A, F, sp_prev,
                        sf_prev, st->metric, st->q, Lall, Rall, fout, guess, out, wcounter(st));
     LAUNCHCHK();
@@ -1315,6 +1373,47 @@ gr_status gr_cfl_dt(const gr_grid *g, const gr_state *st, double *dt_host, hipSt
     if (!(mx > 0.0)) return GR_EINVAL;
     *dt_host = g->cfl / mx;
     return GR_OK;
+}
+
+gr_status gr_timing_start(unsigned kernel_class_mask)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &r : g_trecs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_trecs.clear();
+    g_tmask = kernel_class_mask;
+    return GR_OK;
+}
+
+gr_status gr_timing_read(int kernel_class, double *total_ms, long *launches, double *alg_bytes)
+{
+    if (kernel_class < 0 || kernel_class >= KC_COUNT || !total_ms || !launches || !alg_bytes) return GR_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    double ms = 0.0, by = 0.0;
+    long n = 0;
+    for (auto &r : g_trecs) {
+        if (r.cls != kernel_class) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return GR_EHIP;
+        float e = 0.0f;
+        if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) return GR_EHIP;
+        ms += e;
+        by += r.bytes;
+        n++;
+    }
+    *total_ms = ms;
+    *launches = n;
+    *alg_bytes = by;
+    return GR_OK;
+}
+
+const char *gr_kernel_class_name(int kernel_class)
+{
+    static const char *names[KC_COUNT] = {"k_face_flux", "k_face_E", "k_edge_emf", "k_face_update", "k_cell_update",
+                                          "k_ghost"};
+    if (kernel_class < 0 || kernel_class >= KC_COUNT) return "";
+    return names[kernel_class];
 }
 
 gr_status gr_fail_count(const gr_grid *g, const gr_state *st, unsigned long long *count, hipStream_t s)

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libgrmhd.so")
 GR_OK, GR_EINVAL, GR_ENOMEM, GR_EHIP, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
 EXPORTED = ["gr_abi_version", "gr_strerror", "gr_validate", "gr_field_stride", "gr_workspace_bytes",
             "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim", "gr_divB_norm",
-            "gr_cfl_dt", "gr_fail_count"]
+            "gr_cfl_dt", "gr_fail_count", "gr_timing_start", "gr_timing_read", "gr_kernel_class_name"]
 
 
 class GrError(RuntimeError):
@@ -69,7 +69,11 @@ def lib():
         L.gr_divB_norm.argtypes = [G, S, V, V]
         L.gr_cfl_dt.argtypes = [G, S, D, V]
         L.gr_fail_count.argtypes = [G, S, ctypes.POINTER(ctypes.c_ulonglong), V]
-        for name in ("gr_validate", "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim",
+        L.gr_timing_start.argtypes = [ctypes.c_uint]
+        L.gr_timing_read.argtypes = [ctypes.c_int, D, ctypes.POINTER(ctypes.c_long), D]
+        L.gr_kernel_class_name.argtypes = [ctypes.c_int]
+        L.gr_kernel_class_name.restype = ctypes.c_char_p
+        for name in ("gr_timing_start", "gr_timing_read", "gr_validate", "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim",
                      "gr_divB_norm", "gr_cfl_dt", "gr_fail_count"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -144,6 +148,22 @@ def gr_fail_count(grid, state, stream):
     c = ctypes.c_ulonglong(0)
     _chk(lib().gr_fail_count(ctypes.byref(grid), ctypes.byref(state), ctypes.byref(c), ctypes.c_void_p(stream)))
     return c.value
+
+
+def gr_timing_start(mask):
+    _chk(lib().gr_timing_start(mask))
+
+
+def gr_timing_read(kernel_class):
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_long(0)
+    by = ctypes.c_double(0.0)
+    _chk(lib().gr_timing_read(kernel_class, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+    return ms.value, n.value, by.value
+
+
+def gr_kernel_class_name(kernel_class):
+    return lib().gr_kernel_class_name(kernel_class).decode()
 
 
 # ---------------------------------------------------------------------------
