@@ -1,0 +1,165 @@
+// common.h -- grid geometry, launch regions and reconstructions shared by the
+// gfx950 kernels.  32-bit indices inside one field (a field holds < 2^31
+// points), uniform (scalar) field base pointers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/grmhd.h"
+
+namespace gr {
+
+struct Geo {
+    int N[3], g[3], n[3], act[3];
+    int st[3];   // index stride per direction: 1, Nx, Nx Ny
+    long fs;     // field stride (doubles) of a field block
+    double dx[3], idx[3];
+};
+
+template <int K>
+struct Ptr {
+    double *p[K];
+};
+template <int K>
+struct CPtr {
+    const double *p[K];
+};
+
+// a box of points [lo, lo + cnt): 1-D blocks run over the (x, y) plane
+// (x fastest, so consecutive lanes touch consecutive addresses) and
+// blockIdx.y runs over z
+struct Region {
+    int lo[3], cnt[3];
+};
+
+__device__ __forceinline__ bool region_point(const Region &R, int c[3])
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= R.cnt[0] * R.cnt[1]) return false;
+    int y = t / R.cnt[0];
+    c[0] = R.lo[0] + (t - y * R.cnt[0]);
+    c[1] = R.lo[1] + y;
+    c[2] = R.lo[2] + (int)blockIdx.y;
+    return true;
+}
+
+__device__ __forceinline__ int lin(const Geo &G, const int c[3]) { return c[0] + G.st[1] * c[1] + G.st[2] * c[2]; }
+
+// loads / stores at a 32-bit byte offset from a uniform base pointer: the
+// address is formed by the memory instruction (scalar base + vector offset)
+// instead of a 64-bit vector add per pointer
+__device__ __forceinline__ double ldb(const double *p, unsigned off) { return *(const double *)((const char *)p + off); }
+__device__ __forceinline__ void stb(double *p, unsigned off, double v) { *(double *)((char *)p + off) = v; }
+
+// reciprocal: hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r); for the positive, bounded denominators of the
+// point-wise solvers (a few ulp, no IEEE special-case handling)
+__device__ __forceinline__ double frcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// ---------------------------------------------------------------------------
+// reconstruction (Sec 5: minmod, MC, PPM).  Per-cell form: the left and right
+// interface values (aL, aR) of cell 0 from its neighbours a[-2..2].
+__device__ __forceinline__ double minmod2(double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    return fabs(a) < fabs(b) ? a : b;
+}
+__device__ __forceinline__ double minmod3(double a, double b, double c)
+{
+    if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+    if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+    return 0.0;
+}
+// Colella-Woodward fourth-order interface value, clipped between neighbours
+__device__ __forceinline__ double ppm_iface(double am1, double a0, double a1, double a2)
+{
+    double v = 7.0 / 12.0 * (a0 + a1) - 1.0 / 12.0 * (am1 + a2);
+    double lo = fmin(a0, a1), hi = fmax(a0, a1);
+    return fmin(fmax(v, lo), hi);
+}
+// the two CW monotonicity constraints (no steepening, no flattening)
+__device__ __forceinline__ void ppm_mono(double a, double &aL, double &aR)
+{
+    if ((aR - a) * (a - aL) <= 0.0) {
+        aL = a;
+        aR = a;
+        return;
+    }
+    // the two tests are continuous at their thresholds (the modified value
+    // equals the unmodified one there), so d^2/6 may be formed as d^2 * (1/6)
+    double d = aR - aL, m = a - 0.5 * (aL + aR);
+    double d26 = d * d * (1.0 / 6.0);
+    if (d * m > d26) aL = 3.0 * a - 2.0 * aR;
+    else if (-d26 > d * m) aR = 3.0 * a - 2.0 * aL;
+}
+
+template <int REC>
+__device__ __forceinline__ void recon_cell(double am2, double am1, double a0, double ap1, double ap2, double &aL,
+                                          double &aR)
+{
+    if (REC == GR_MINMOD) {
+        double s = minmod2(a0 - am1, ap1 - a0);
+        aL = a0 - 0.5 * s;
+        aR = a0 + 0.5 * s;
+    } else if (REC == GR_MC) {
+        double s = minmod3(0.5 * (ap1 - am1), 2.0 * (a0 - am1), 2.0 * (ap1 - a0));
+        aL = a0 - 0.5 * s;
+        aR = a0 + 0.5 * s;
+    } else {
+        aL = ppm_iface(am2, am1, a0, ap1);
+        aR = ppm_iface(am1, a0, ap1, ap2);
+        ppm_mono(a0, aL, aR);
+    }
+}
+
+// face form: the left state (right value of the cell below) and the right
+// state (left value of the cell above) at the face between w[2] and w[3];
+// PPM shares the interface value of the face itself between the two cells
+template <int REC>
+__device__ __forceinline__ void recon_face(const double w[6], double &L, double &R)
+{
+    if (REC == GR_PPM) {
+        double i1 = ppm_iface(w[0], w[1], w[2], w[3]);
+        double i2 = ppm_iface(w[1], w[2], w[3], w[4]);
+        double i3 = ppm_iface(w[2], w[3], w[4], w[5]);
+        double aL = i1, aR = i2;
+        ppm_mono(w[2], aL, aR);
+        L = aR;
+        aL = i2;
+        aR = i3;
+        ppm_mono(w[3], aL, aR);
+        R = aL;
+    } else {
+        double t;
+        recon_cell<REC>(w[0], w[1], w[2], w[3], w[4], t, L);
+        recon_cell<REC>(w[1], w[2], w[3], w[4], w[5], R, t);
+    }
+}
+
+// window of one field along stride s around index id (face id between id-s and id)
+template <int REC>
+__device__ __forceinline__ void recon_at(const double *__restrict__ a, int id, int s, double &L, double &R)
+{
+    double w[6];
+    unsigned o = (unsigned)id << 3, sb = (unsigned)s << 3;
+    w[1] = ldb(a, o - 2 * sb);
+    w[2] = ldb(a, o - sb);
+    w[3] = ldb(a, o);
+    w[4] = ldb(a, o + sb);
+    if (REC == GR_PPM) {
+        w[0] = ldb(a, o - 3 * sb);
+        w[5] = ldb(a, o + 2 * sb);
+    } else {
+        w[0] = w[1];
+        w[5] = w[4];
+    }
+    recon_face<REC>(w, L, R);
+}
+
+}  // namespace gr

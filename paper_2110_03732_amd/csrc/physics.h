@@ -11,11 +11,14 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "common.h"
+
 namespace gr {
 
 struct Phys {
     double gam;      // adiabatic index Gamma
     double G1;       // Gamma / (Gamma - 1)
+    double iG1;      // 1 / G1
     double rho_atm, p_atm, D_atm;  // atmosphere state, D threshold
     double tol;      // Newton tolerance
     int maxit;
@@ -23,17 +26,13 @@ struct Phys {
     double eta, sigma0, eta_min, eta_max;
 };
 
-__device__ __forceinline__ double sq(double x) { return x * x; }
-
-// flat-frame primitive state -> conserved (D, S_x..z, tau) and the flux in
+// flat-frame primitive state -> conserved (D, S, tau, E) and the flux in
 // direction d (f_D, f_S, f_tau, f_E); Sec 2.1 with alpha = psi = 1
-struct Cons { double D, S[3], tau; };
-
 __device__ __forceinline__ void flat_cons_flux(const Phys &P, int d, double rho, const double u[3], double p,
                                                const double E[3], const double B[3], double q[8], double f[8])
 {
     double W = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    double iW = 1.0 / W;
+    double iW = frcp(W);
     double v[3] = {u[0] * iW, u[1] * iW, u[2] * iW};
     double rhoh = rho + P.G1 * p;
     double w = rhoh * W * W;   // rho h W^2
@@ -83,65 +82,66 @@ __device__ __forceinline__ double cell_eta(const Phys &P, double Dund)
 // f(u) = w~ u - (S - E x B), w~ = [W (tau + D - U) - D/G1]/(W^2 - 1/G1).
 // Newton with the analytic Jacobian, 3x3 solve by the adjugate, backtracking
 // line search on F = f.f/2 (Armijo 1e-4, quadratic model, cut in [0.1, 0.5]).
-// Returns 0 converged, 1 not converged.  u (in: guess, out: root), E, wt.
 struct ImpSys {
-    double D, tau, S[3], Es[3], B[3], et, G1;
+    double D, tau, S[3], Es[3], B[3], et, iG1, B2;
+};
+// everything the Jacobian needs from one residual evaluation
+struct ImpEval {
+    double f[3], E[3], wt, W, iW, r1, iA0, iden, Esu, U;
 };
 
-__device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], double f[3], double E[3], double &wt,
-                                         double &W)
+__device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], ImpEval &e)
 {
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    W = sqrt(1.0 + uu);
-    double A0 = W + s.et, A1 = s.et / (1.0 + s.et * W);
-    double Esu = s.Es[0] * u[0] + s.Es[1] * u[1] + s.Es[2] * u[2];
+    e.W = sqrt(1.0 + uu);
+    e.iW = frcp(e.W);
+    e.r1 = frcp(1.0 + s.et * e.W);  // A1 = et r1
+    e.iA0 = frcp(e.W + s.et);
+    e.Esu = s.Es[0] * u[0] + s.Es[1] * u[1] + s.Es[2] * u[2];
+    double A1 = s.et * e.r1;
     double uxB[3] = {u[1] * s.B[2] - u[2] * s.B[1], u[2] * s.B[0] - u[0] * s.B[2], u[0] * s.B[1] - u[1] * s.B[0]};
-    double iA0 = 1.0 / A0;
 #pragma unroll
-    for (int i = 0; i < 3; i++) E[i] = (s.et * s.Es[i] + A1 * Esu * u[i] - uxB[i]) * iA0;
-    double U = 0.5 * (E[0] * E[0] + E[1] * E[1] + E[2] * E[2] + s.B[0] * s.B[0] + s.B[1] * s.B[1] + s.B[2] * s.B[2]);
-    double den = W * W - 1.0 / s.G1;
-    wt = (W * (s.tau + s.D - U) - s.D / s.G1) / den;
-    double ExB[3] = {E[1] * s.B[2] - E[2] * s.B[1], E[2] * s.B[0] - E[0] * s.B[2], E[0] * s.B[1] - E[1] * s.B[0]};
+    for (int i = 0; i < 3; i++) e.E[i] = (s.et * s.Es[i] + A1 * e.Esu * u[i] - uxB[i]) * e.iA0;
+    e.U = 0.5 * (e.E[0] * e.E[0] + e.E[1] * e.E[1] + e.E[2] * e.E[2] + s.B2);
+    e.iden = frcp(e.W * e.W - s.iG1);
+    e.wt = (e.W * (s.tau + s.D - e.U) - s.D * s.iG1) * e.iden;
+    double ExB[3] = {e.E[1] * s.B[2] - e.E[2] * s.B[1], e.E[2] * s.B[0] - e.E[0] * s.B[2],
+                     e.E[0] * s.B[1] - e.E[1] * s.B[0]};
 #pragma unroll
-    for (int i = 0; i < 3; i++) f[i] = wt * u[i] - (s.S[i] - ExB[i]);
+    for (int i = 0; i < 3; i++) e.f[i] = e.wt * u[i] - (s.S[i] - ExB[i]);
 }
 
-__device__ __forceinline__ void imp_jac(const ImpSys &s, const double u[3], const double E[3], double wt, double W,
-                                        double J[3][3])
+__device__ __forceinline__ void imp_jac(const ImpSys &s, const double u[3], const ImpEval &e, double J[3][3])
 {
-    double et = s.et;
-    double A0 = W + et, opW = 1.0 + et * W, A1 = et / opW, A1d = -et * et / (opW * opW);
-    double Esu = s.Es[0] * u[0] + s.Es[1] * u[1] + s.Es[2] * u[2];
-    double iA0W = 1.0 / (A0 * W);
+    double A1 = s.et * e.r1, A1d = -s.et * s.et * e.r1 * e.r1;
+    double iA0W = e.iA0 * e.iW;
     double dE[3][3];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            double t = -E[i] * u[j] + A1 * W * u[i] * s.Es[j] + (A1 * W * (i == j ? 1.0 : 0.0) + A1d * u[i] * u[j]) * Esu;
+            double t = -e.E[i] * u[j] + A1 * e.W * u[i] * s.Es[j] +
+                       (A1 * e.W * (i == j ? 1.0 : 0.0) + A1d * u[i] * u[j]) * e.Esu;
             // - W eps_{i j m} B_m
-            int m = 3 - i - j;
             if (i != j) {
-                double e = ((j - i + 3) % 3 == 1) ? 1.0 : -1.0;
-                t -= W * e * s.B[m];
+                int m = 3 - i - j;
+                double sg = ((j - i + 3) % 3 == 1) ? 1.0 : -1.0;
+                t -= e.W * sg * s.B[m];
             }
             dE[i][j] = t * iA0W;
         }
-    double U = 0.5 * (E[0] * E[0] + E[1] * E[1] + E[2] * E[2] + s.B[0] * s.B[0] + s.B[1] * s.B[1] + s.B[2] * s.B[2]);
-    double den = W * W - 1.0 / s.G1;
-    double tDU = s.tau + s.D - U;
+    double tDU = (s.tau + s.D - e.U) * e.iW;
 #pragma unroll
     for (int j = 0; j < 3; j++) {
-        double dU = E[0] * dE[0][j] + E[1] * dE[1][j] + E[2] * dE[2][j];
-        double dw = (tDU * u[j] / W - 2.0 * wt * u[j] - W * dU) / den;
+        double dU = e.E[0] * dE[0][j] + e.E[1] * dE[1][j] + e.E[2] * dE[2][j];
+        double dw = (tDU * u[j] - 2.0 * e.wt * u[j] - e.W * dU) * e.iden;
         // d(E x B)_i/du_j = eps_{ilm} dE_l/du_j B_m
         double dxB0 = dE[1][j] * s.B[2] - dE[2][j] * s.B[1];
         double dxB1 = dE[2][j] * s.B[0] - dE[0][j] * s.B[2];
         double dxB2 = dE[0][j] * s.B[1] - dE[1][j] * s.B[0];
-        J[0][j] = (j == 0 ? wt : 0.0) + u[0] * dw + dxB0;
-        J[1][j] = (j == 1 ? wt : 0.0) + u[1] * dw + dxB1;
-        J[2][j] = (j == 2 ? wt : 0.0) + u[2] * dw + dxB2;
+        J[0][j] = (j == 0 ? e.wt : 0.0) + u[0] * dw + dxB0;
+        J[1][j] = (j == 1 ? e.wt : 0.0) + u[1] * dw + dxB1;
+        J[2][j] = (j == 2 ? e.wt : 0.0) + u[2] * dw + dxB2;
     }
 }
 
@@ -165,15 +165,15 @@ __device__ __forceinline__ bool solve3(const double J[3][3], const double b[3], 
     return true;
 }
 
-__device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int maxit, double u[3], double E[3],
-                                              double &wt, double &W)
+// returns 0 converged, 1 not converged; u: guess in, root out
+__device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int maxit, double u[3], ImpEval &e)
 {
-    double f[3], J[3][3];
-    imp_eval(s, u, f, E, wt, W);
-    double F = 0.5 * (f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    double J[3][3];
+    imp_eval(s, u, e);
+    double F = 0.5 * (e.f[0] * e.f[0] + e.f[1] * e.f[1] + e.f[2] * e.f[2]);
     for (int it = 0; it < maxit; it++) {
-        imp_jac(s, u, E, wt, W, J);
-        double mf[3] = {-f[0], -f[1], -f[2]}, dx[3];
+        imp_jac(s, u, e, J);
+        double mf[3] = {-e.f[0], -e.f[1], -e.f[2]}, dx[3];
         if (!solve3(J, mf, dx)) return 1;
         double dmax = fmax(fabs(dx[0]), fmax(fabs(dx[1]), fabs(dx[2])));
         double umax = fmax(fabs(u[0]), fmax(fabs(u[1]), fabs(u[2])));
@@ -181,17 +181,18 @@ __device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int m
             u[0] += dx[0];
             u[1] += dx[1];
             u[2] += dx[2];
-            imp_eval(s, u, f, E, wt, W);
+            imp_eval(s, u, e);
             return 0;
         }
-        double slope = -2.0 * F, lam = 1.0, un[3], fn[3], En[3], wn, Wn, Fn = 0.0;
+        double slope = -2.0 * F, lam = 1.0, un[3], Fn = 0.0;
+        ImpEval en;
         bool ok = false;
         for (int ls = 0; ls < 60; ls++) {
             un[0] = u[0] + lam * dx[0];
             un[1] = u[1] + lam * dx[1];
             un[2] = u[2] + lam * dx[2];
-            imp_eval(s, un, fn, En, wn, Wn);
-            Fn = 0.5 * (fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]);
+            imp_eval(s, un, en);
+            Fn = 0.5 * (en.f[0] * en.f[0] + en.f[1] * en.f[1] + en.f[2] * en.f[2]);
             if (isfinite(Fn) && Fn <= F + 1e-4 * lam * slope) {
                 ok = true;
                 break;
@@ -205,14 +206,7 @@ __device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int m
         u[0] = un[0];
         u[1] = un[1];
         u[2] = un[2];
-        f[0] = fn[0];
-        f[1] = fn[1];
-        f[2] = fn[2];
-        E[0] = En[0];
-        E[1] = En[1];
-        E[2] = En[2];
-        wt = wn;
-        W = Wn;
+        e = en;
         F = Fn;
     }
     return 1;
@@ -222,7 +216,6 @@ __device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int m
 // g(p) = (Gamma-1) rho eps(p) - p with v = S_f/(tau_f + D + p), rho = D/W,
 // rho eps = [tau_f + D (1 - W) + p (1 - W^2)]/W^2, by Newton steps kept inside
 // a shrinking sign bracket (bisection when a step leaves it).
-// Returns 0 ok (p, W, Z = tau_f + D + p), 1 no physical root.
 __device__ __forceinline__ double c2p_g(double gm1, double p, double D, double tauf, double Sf2, double &dg,
                                         double &W)
 {
@@ -236,7 +229,7 @@ __device__ __forceinline__ double c2p_g(double gm1, double p, double D, double t
     }
     double iW2 = 1.0 - v2;
     double iW = sqrt(iW2);
-    W = 1.0 / iW;
+    W = frcp(iW);
     double rhoeps = (tauf + D) * iW2 - D * iW + p * (iW2 - 1.0);
     double a = 2.0 * Sf2 * iZ * iZ * iZ;  // d(1/W^2)/dp
     double drhoeps = (tauf + D) * a - D * W * 0.5 * a + (iW2 - 1.0) + p * a;
@@ -244,6 +237,7 @@ __device__ __forceinline__ double c2p_g(double gm1, double p, double D, double t
     return gm1 * rhoeps - p;
 }
 
+// returns 0 ok (p, W), 1 no physical root
 __device__ __forceinline__ int c2p_pressure(double gm1, double D, double tauf, double Sf2, double pguess, double &p,
                                             double &W)
 {
