@@ -41,7 +41,9 @@ def time_steps(run, dt, steps, torch):
 def kernel_roofline(run, dt, steps, grmhd, torch):
     """replay of the timed steps with every kernel class bracketed by HIP
     events on the run's stream; roofline of the class with the largest time"""
-    n_cls = 6
+    n_cls = 0
+    while grmhd.gr_kernel_class_name(n_cls):
+        n_cls += 1
     grmhd.gr_timing_start((1 << n_cls) - 1)
     torch.cuda.synchronize()
     for _ in range(steps):
@@ -85,6 +87,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128, help="cells per direction of the star workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true", help="star workload only (no 2-D point, no roofline replay)")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="end with a plain 256 MiB device copy, the reference kernel for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one MI355X only; runs on more than one GPU are not supported "
@@ -108,20 +113,28 @@ def main():
     ms = time_steps(run, dt, args.steps, torch)
     ms_per_step = ms / args.steps
     value = s.ncells * args.steps / (ms * 1e-3)
-    kname, roof, per_kernel = kernel_roofline(run, dt, args.steps, grmhd, torch)
     fails = run.fail_count()
     div = run.divB()
-
-    # the 2-D blast wave (512^2, PPM + SSP3) as a second plain-path point
-    sb = W.blast_wave(512, eta=1e-6)
-    rb = grmhd.Run(sb, device="cuda:0")
-    dtb = rb.dt()
-    for _ in range(args.warmup):
-        rb.step(dtb)
-    msb = time_steps(rb, dtb, args.steps, torch)
-    extra = {"blast_512sq_ssp3_zone_cycles_per_s": round(sb.ncells * args.steps / (msb * 1e-3), 1),
-             "blast_512sq_ms_per_step": round(msb / args.steps, 4),
-             "per_kernel": per_kernel, "recovery_failures": int(fails), "divB_linf": float(div[2])}
+    extra = {"recovery_failures": int(fails), "divB_linf": float(div[2])}
+    roof = None
+    if not args.no_extra:
+        kname, roof, per_kernel = kernel_roofline(run, dt, args.steps, grmhd, torch)
+        # the 2-D blast wave (512^2, PPM + SSP3) as a second plain-path point
+        sb = W.blast_wave(512, eta=1e-6)
+        rb = grmhd.Run(sb, device="cuda:0")
+        dtb = rb.dt()
+        for _ in range(args.warmup):
+            rb.step(dtb)
+        msb = time_steps(rb, dtb, args.steps, torch)
+        extra.update({"blast_512sq_ssp3_zone_cycles_per_s": round(sb.ncells * args.steps / (msb * 1e-3), 1),
+                      "blast_512sq_ms_per_step": round(msb / args.steps, 4), "per_kernel": per_kernel})
+    if args.copy_ref:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        extra["copy_ref_bytes"] = 2 * a.numel() * 8
     out = {
         "metric": "zone-cycles/s per IMEX-RK step FP64 (plain single grid)",
         "value": round(value, 1),

@@ -31,14 +31,38 @@ struct Region {
     int lo[3], cnt[3];
 };
 
+// XCD-aware block order.  Workgroups are dealt round-robin to the 8 XCDs
+// (dispatch id i runs on XCD i mod 8), each with its own L2.  Renumbering so
+// that XCD x receives the contiguous run [x P, (x + 1) P) of logical blocks
+// keeps stencil neighbours (adjacent rows, planes and tiles) in one L2.  The
+// tail of a grid that does not divide by 8 keeps its order.
+constexpr int kXcd = 8;
+__device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by, unsigned &bz)
+{
+    unsigned gx = gridDim.x, gy = gridDim.y;
+    unsigned total = gx * gy * gridDim.z;
+    unsigned L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    unsigned per = total / kXcd;
+    if (L < per * kXcd) L = (L % kXcd) * per + L / kXcd;
+    bx = L % gx;
+    unsigned r = L / gx;
+    by = r % gy;
+    bz = r / gy;
+}
+
+// XCD: renumber blocks for kernels that read stencils; streaming kernels keep
+// the dispatch order
+template <bool XCD = false>
 __device__ __forceinline__ bool region_point(const Region &R, int c[3])
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    if (XCD) xcd_block(bx, by, bz);
+    int t = bx * blockDim.x + threadIdx.x;
     if (t >= R.cnt[0] * R.cnt[1]) return false;
     int y = t / R.cnt[0];
     c[0] = R.lo[0] + (t - y * R.cnt[0]);
     c[1] = R.lo[1] + y;
-    c[2] = R.lo[2] + (int)blockIdx.y;
+    c[2] = R.lo[2] + (int)by;
     return true;
 }
 

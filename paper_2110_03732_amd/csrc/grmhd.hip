@@ -34,9 +34,8 @@ namespace {
 // measurement hook: launches of the selected kernel classes are bracketed by
 // HIP events on the stream they are launched on, with the algorithmic bytes
 // (every live input field read once, every output written once) of the launch
-enum KClass { KC_SWEEP = 0, KC_FACE_E, KC_EDGE_EMF, KC_FACE_UPDATE, KC_CELL_UPDATE, KC_GHOST, KC_COUNT };
-const char *kClassNames[KC_COUNT] = {"k_sweep", "k_face_E", "k_edge_emf", "k_face_update", "k_cell_update",
-                                     "k_ghost_all"};
+enum KClass { KC_SWEEP = 0, KC_CT, KC_FACE_UPDATE, KC_CELL_UPDATE, KC_GHOST, KC_COUNT };
+const char *kClassNames[KC_COUNT] = {"k_xy", "k_ct", "k_face_update", "k_cell_update", "k_ghost_all"};
 struct TRec {
     int cls;
     hipEvent_t a, b;
@@ -171,7 +170,7 @@ constexpr size_t kHeader = 1 << 20;  // failure counter + reduction partials
 constexpr int kMaxParts = 4096;
 
 struct Layout {
-    size_t sprim, sface, L, R, F, Ef, EM, total_fields;
+    size_t sprim, sface, L, R, Lxy, EM, total_fields;
 };
 
 Layout layout(const gr_grid *g)
@@ -187,10 +186,8 @@ Layout layout(const gr_grid *g)
     o += 11 * (size_t)T.s;
     L.R = o;
     o += 3 * (size_t)T.s;
-    L.F = o;
-    o += 24;
-    L.Ef = o;
-    o += 6;
+    L.Lxy = o;
+    o += 8;
     L.EM = o;
     o += 3;
     L.total_fields = o;
@@ -302,67 +299,54 @@ gr_status ghost_fill(const gr_grid *g, const Geo &G, double *cells, double *face
     return GR_OK;
 }
 
-template <int REC, int MET, int D>
-gr_status launch_sweep(const Geo &G, const Phys &P, const double *sp, const double *sf, const double *met, double *F,
-                       hipStream_t s)
+// x (and y) phases of the explicit operator; 1-D grids take a one-row tile
+template <int REC, int MET>
+gr_status launch_xy(const Geo &G, const Phys &P, const double *sp, const double *sf, const double *met, double *Lxy,
+                    hipStream_t s)
 {
-    constexpr int TX = Tile<D>::TX, TY = Tile<D>::TY, TZ = Tile<D>::TZ;
-    dim3 grid((G.n[0] + TX - 1) / TX, (G.n[1] + TY - 1) / TY, (G.n[2] + TZ - 1) / TZ);
-    const int r = (REC == GR_PPM) ? 3 : 2;
-    double faces = (double)(G.n[0] + (D == 0)) * (G.n[1] + (D == 1)) * (G.n[2] + (D == 2));
-    double cells = (double)G.n[0] * G.n[1] * G.n[2] / G.n[D] * (G.n[D] + 2 * r);
-    // reads: 8 stage fields + 2 transverse face fields + metric per cell, the
-    // normal face field per face; writes: 8 fluxes per face
-    {
-        TScope ts(KC_SWEEP, s, 8.0 * (cells * (8 + 2 + 2 * MET) + faces * (1 + 8)));
-        hipLaunchKernelGGL((k_sweep<REC, MET, D>), grid, dim3(kBlock), 0, s, G, P, cptrs<8>(sp, G.fs),
-                           cptrs<3>(sf, G.fs), cptrs<2>(met, G.fs), ptrs<8>(F, G.fs));
-        LAUNCHCHK();
+    // reads: 8 stage fields, 3 face fields and the metric per cell; writes 8
+    TScope ts(KC_SWEEP, s, 8.0 * G.n[0] * G.n[1] * G.n[2] * (8 + 3 + 2 * MET + 8));
+    if (G.act[1]) {
+        constexpr int TX = 32, TY = 8;
+        dim3 grid((G.n[0] + TX - 1) / TX, (G.n[1] + TY - 1) / TY, G.n[2]);
+        hipLaunchKernelGGL((k_xy<REC, MET, TX, TY>), grid, dim3(TX * TY), 0, s, G, P, cptrs<8>(sp, G.fs),
+                           cptrs<3>(sf, G.fs), cptrs<2>(met, G.fs), ptrs<8>(Lxy, G.fs));
+    } else {
+        constexpr int TX = 256, TY = 1;
+        dim3 grid((G.n[0] + TX - 1) / TX, G.n[1], G.n[2]);
+        hipLaunchKernelGGL((k_xy<REC, MET, TX, TY>), grid, dim3(TX * TY), 0, s, G, P, cptrs<8>(sp, G.fs),
+                           cptrs<3>(sf, G.fs), cptrs<2>(met, G.fs), ptrs<8>(Lxy, G.fs));
     }
-    // the upper boundary face of every line along D
-    Region R;
-    for (int d = 0; d < 3; d++) {
-        R.lo[d] = G.g[d];
-        R.cnt[d] = G.n[d];
-    }
-    R.lo[D] = G.g[D] + G.n[D];
-    R.cnt[D] = 1;
-    dim3 gr, bl;
-    launch_dims(R, gr, bl);
-    hipLaunchKernelGGL((k_last_face<REC, MET, D>), gr, bl, 0, s, G, P, R, cptrs<8>(sp, G.fs), cptrs<3>(sf, G.fs),
-                       cptrs<2>(met, G.fs), ptrs<8>(F, G.fs));
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+// edge EMFs of direction K on the edges of the interior plus one layer in a and b
+template <int REC, int MET, int K>
+gr_status launch_ct(const Geo &G, const double *met, const double *sp, const double *sf, double *EM, hipStream_t s)
+{
+    constexpr int a = (K + 1) % 3, b = (K + 2) % 3;
+    if (!G.act[a] && !G.act[b]) return GR_OK;
+    Region Re = region(G, (1 << a) | (1 << b));
+    const int *T = CtTile<K>::T;
+    dim3 grid((Re.cnt[0] + T[0] - 1) / T[0], (Re.cnt[1] + T[1] - 1) / T[1], (Re.cnt[2] + T[2] - 1) / T[2]);
+    // reads E_k, q_B^a, q_B^b and the metric per edge point; writes one EMF
+    TScope ts(KC_CT, s, 8.0 * rtotal(Re) * (3 + 2 * MET + 1));
+    hipLaunchKernelGGL((k_ct<REC, MET, K>), grid, dim3(kBlock), 0, s, G, Re, sp + (5 + K) * G.fs, cptrs<3>(sf, G.fs),
+                       cptrs<2>(met, G.fs), EM + (size_t)K * G.fs);
     LAUNCHCHK();
     return GR_OK;
 }
 
 template <int REC, int MET>
-gr_status launch_L(const Geo &G, const Phys &P, const double *met, const double *sp, const double *sf, double *F,
-                   double *Ef, double *EM, hipStream_t s)
+gr_status launch_L(const Geo &G, const Phys &P, const double *met, const double *sp, const double *sf, double *Lxy,
+                   double *EM, hipStream_t s)
 {
     gr_status r;
-    if (G.act[0] && (r = launch_sweep<REC, MET, 0>(G, P, sp, sf, met, F, s)) != GR_OK) return r;
-    if (G.act[1] && (r = launch_sweep<REC, MET, 1>(G, P, sp, sf, met, F + 8 * G.fs, s)) != GR_OK) return r;
-    if (G.act[2] && (r = launch_sweep<REC, MET, 2>(G, P, sp, sf, met, F + 16 * G.fs, s)) != GR_OK) return r;
-    for (int k = 0; k < 3; k++) {
-        int a = (k + 1) % 3, b = (k + 2) % 3;
-        if (!G.act[a] && !G.act[b]) continue;
-        Region Rf = region(G, 1 << a, 1 << b);
-        double *EfL = Ef + (size_t)(2 * k) * G.fs, *EfR = Ef + (size_t)(2 * k + 1) * G.fs;
-        dim3 gr, bl;
-        {
-            TScope ts(KC_FACE_E, s, 8.0 * rtotal(Rf) * (1 + 2 * MET + 2));
-            launch_dims(Rf, gr, bl);
-            hipLaunchKernelGGL((k_face_E<REC, MET>), gr, bl, 0, s, G, k, Rf, sp + (5 + k) * G.fs,
-                               cptrs<2>(met, G.fs), EfL, EfR);
-            LAUNCHCHK();
-        }
-        Region Re = region(G, (1 << a) | (1 << b));
-        TScope ts(KC_EDGE_EMF, s, 8.0 * (2.0 * rtotal(Rf) + rtotal(Re) * (2 + 2 * MET + 1)));
-        launch_dims(Re, gr, bl);
-        hipLaunchKernelGGL((k_edge_emf<REC, MET>), gr, bl, 0, s, G, k, Re, cptrs<3>(sf, G.fs), cptrs<2>(met, G.fs),
-                           EfL, EfR, EM + (size_t)k * G.fs);
-        LAUNCHCHK();
-    }
+    if ((r = launch_xy<REC, MET>(G, P, sp, sf, met, Lxy, s)) != GR_OK) return r;
+    if ((r = launch_ct<REC, MET, 2>(G, met, sp, sf, EM, s)) != GR_OK) return r;
+    if ((r = launch_ct<REC, MET, 0>(G, met, sp, sf, EM, s)) != GR_OK) return r;
+    if ((r = launch_ct<REC, MET, 1>(G, met, sp, sf, EM, s)) != GR_OK) return r;
     return GR_OK;
 }
 
@@ -395,12 +379,12 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
     };
     double *sp_prev = (p >= 1) ? wfield(st, G, Ly.sprim + 8 * (size_t)(p - 1)) : nullptr;
     double *sf_prev = (p >= 1) ? stage_face(p - 1) : nullptr;
-    double *F = wfield(st, G, Ly.F), *Ef = wfield(st, G, Ly.Ef), *EM = wfield(st, G, Ly.EM);
+    double *Lxy = wfield(st, G, Ly.Lxy), *EM = wfield(st, G, Ly.EM);
     const double *met = st->metric;
     if (withL) {
         gr_status r = ghost_fill(g, G, sp_prev, sf_prev, s);
         if (r != GR_OK) return r;
-        r = launch_L<REC, MET>(G, P, met, sp_prev, sf_prev, F, Ef, EM, s);
+        r = launch_L<REC, MET>(G, P, met, sp_prev, sf_prev, Lxy, EM, s);
         if (r != GR_OK) return r;
     }
     // faces of this pass
@@ -411,26 +395,27 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
         if (A.cR[j] != 0.0) nRst++;
     }
     if (fin || !faces_are_n(T, p)) {
+        Region R = region(G, 7);
+        FaceLs Ls;
+        std::memset(&Ls, 0, sizeof(Ls));
         for (int d = 0; d < 3; d++) {
-            Region R = region(G, 1 << d);
-            FaceLs Ls;
             for (int j = 0; j < 4; j++)
-                Ls.Lf[j] = (j < T.s) ? wfield(st, G, Ly.L + 11 * (size_t)j + 8 + d) : nullptr;
-            double *Lst = withL ? wfield(st, G, Ly.L + 11 * (size_t)(p - 1) + 8 + d) : nullptr;
-            TScope ts(KC_FACE_UPDATE, s, 8.0 * rtotal(R) * (2 * (int)withL + 1 + nLst + 1 + (int)withL));
-            dim3 gr, bl;
-            launch_dims(R, gr, bl);
-            CPtr<3> em = cptrs<3>(EM, G.fs);
-            hipLaunchKernelGGL(k_face_update, gr, bl, 0, s, G, d, R, A, em, st->face + d * G.fs, Ls, Lst,
-                               fout + d * G.fs);
-            LAUNCHCHK();
+                Ls.Lf[j][d] = (j < T.s) ? wfield(st, G, Ly.L + 11 * (size_t)j + 8 + d) : nullptr;
+            Ls.Lst[d] = withL ? wfield(st, G, Ly.L + 11 * (size_t)(p - 1) + 8 + d) : nullptr;
         }
+        double nf = 0.0;
+        for (int d = 0; d < 3; d++) nf += (double)rtotal(region(G, 1 << d));
+        TScope ts(KC_FACE_UPDATE, s, 8.0 * (nf * (1 + nLst + 1 + (int)withL) + (withL ? 3.0 * rtotal(R) : 0.0)));
+        dim3 gr, bl;
+        launch_dims(R, gr, bl);
+        hipLaunchKernelGGL(k_face_update, gr, bl, 0, s, G, R, A, cptrs<3>(EM, G.fs), cptrs<3>(st->face, G.fs), Ls,
+                           ptrs<3>(fout, G.fs));
+        LAUNCHCHK();
     }
     // cells
     CellIO io;
     std::memset(&io, 0, sizeof(io));
-    for (int d = 0; d < 3; d++)
-        for (int v = 0; v < 8; v++) io.F[d][v] = F + (size_t)(8 * d + v) * G.fs;
+    for (int v = 0; v < 8; v++) io.Lxy[v] = Lxy + (size_t)v * G.fs;
     for (int v = 0; v < 8; v++) io.spm[v] = sp_prev ? sp_prev + v * G.fs : nullptr;
     for (int d = 0; d < 3; d++) io.sfm[d] = sf_prev ? sf_prev + d * G.fs : nullptr;
     for (int j = 0; j < T.s; j++) {
@@ -452,13 +437,19 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
     io.nfail = wcounter(st);
     Region Rc = region(G, 0);
     double cb = 8 + 3 + 2 * MET + 8 * nLst + 3 * nRst + (fin ? 1 : 3);  // q, faces, metric, L, R, guess
-    if (withL) cb += 3 * 8 + 8 + 3;                                      // fluxes, stage p-1 prims/E, faces
+    if (withL) cb += 8 + 8 + 3;                                          // Lxy, stage p-1 prims/E, faces
     cb += fin ? (8 + 5) : (8 + 3);                                       // outputs
     if (withL) cb += 8;                                                  // stored L
     TScope ts(KC_CELL_UPDATE, s, 8.0 * rtotal(Rc) * cb);
-    dim3 gr, bl;
-    launch_dims(Rc, gr, bl);
-    hipLaunchKernelGGL((k_cell_update<MET>), gr, bl, 0, s, G, P, Rc, A, io);
+    if (withL && G.act[2]) {
+        constexpr int TX = 16, TZ = 16;
+        dim3 grid((Rc.cnt[0] + TX - 1) / TX, Rc.cnt[1], (Rc.cnt[2] + TZ - 1) / TZ);
+        hipLaunchKernelGGL((k_cell_update<REC, MET, 1, TX, TZ>), grid, dim3(kBlock), 0, s, G, P, Rc, A, io);
+    } else {
+        dim3 gr, bl;
+        launch_dims(Rc, gr, bl);
+        hipLaunchKernelGGL((k_cell_update<REC, MET, 0, 1, 1>), gr, bl, 0, s, G, P, Rc, A, io);
+    }
     LAUNCHCHK();
     return GR_OK;
 }
@@ -595,7 +586,7 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     int Ne0 = G.N[0] + (G.act[0] ? 1 : 0), Ne1 = G.N[1] + (G.act[1] ? 1 : 0), Ne2 = G.N[2] + (G.act[2] ? 1 : 0);
     long es = (long)Ne0 * Ne1 * Ne2;
     double *Ad = nullptr, *fd = nullptr;
-    double *scratch = wfield(st, G, Ly.F);  // 24 fields of scratch
+    double *scratch = wfield(st, G, Ly.L);  // the stored-L block (>= 22 fields) is free before the first step
     if (A_host) {
         if ((size_t)3 * es > (size_t)12 * G.fs) return GR_EINVAL;
         Ad = scratch;
@@ -677,8 +668,8 @@ gr_status gr_con2prim(const gr_grid *g, gr_state *st, hipStream_t s)
     Region Rc = region(G, 0);
     dim3 gr, bl;
     launch_dims(Rc, gr, bl);
-    if (g->metric) hipLaunchKernelGGL(k_cell_update<1>, gr, bl, 0, s, G, P, Rc, A, io);
-    else hipLaunchKernelGGL(k_cell_update<0>, gr, bl, 0, s, G, P, Rc, A, io);
+    if (g->metric) hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 1, 0, 1, 1>), gr, bl, 0, s, G, P, Rc, A, io);
+    else hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 0, 0, 1, 1>), gr, bl, 0, s, G, P, Rc, A, io);
     LAUNCHCHK();
     return GR_OK;
 }

@@ -64,6 +64,34 @@ __device__ __forceinline__ void flat_cons_flux(const Phys &P, int d, double rho,
     f[5 + d2] = -B[d1];
 }
 
+// HLL with unit speeds, F = (f_L + f_R)/2 - (q_R - q_L)/2, accumulated one
+// state at a time: F += (f + sgn q)/2 with sgn = +1 for the left state and -1
+// for the right one (only one state's variables are live at a time)
+template <int d>
+__device__ __forceinline__ void hll_accumulate(const Phys &P, double rho, const double u[3], double p,
+                                               const double E[3], const double B[3], double sgn, double F[8])
+{
+    constexpr int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    double W = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    double iW = frcp(W);
+    double v[3] = {u[0] * iW, u[1] * iW, u[2] * iW};
+    double w = (rho + P.G1 * p) * W * W;
+    double U = 0.5 * (E[0] * E[0] + E[1] * E[1] + E[2] * E[2] + B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    double ExB[3] = {E[1] * B[2] - E[2] * B[1], E[2] * B[0] - E[0] * B[2], E[0] * B[1] - E[1] * B[0]};
+    double D = rho * W;
+    double S[3] = {w * v[0] + ExB[0], w * v[1] + ExB[1], w * v[2] + ExB[2]};
+    double vd = v[d];
+    double pt = p + U;
+    F[0] += 0.5 * (D * vd + sgn * D);
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+        F[1 + j] += 0.5 * (w * vd * v[j] - E[d] * E[j] - B[d] * B[j] + (j == d ? pt : 0.0) + sgn * S[j]);
+    F[4] += 0.5 * (S[d] - vd * D + sgn * (w - p + U - D));
+    F[5 + d] += 0.5 * sgn * E[d];
+    F[5 + d1] += 0.5 * (B[d2] + sgn * E[d1]);
+    F[5 + d2] += 0.5 * (-B[d1] + sgn * E[d2]);
+}
+
 // resistivity of a cell: uniform, or 1/sigma_c of eq. sigma_D clamped to
 // [eta_min, eta_max], with D_atmo the atmosphere threshold D_atm
 __device__ __forceinline__ double cell_eta(const Phys &P, double Dund)

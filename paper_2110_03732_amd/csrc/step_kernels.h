@@ -2,13 +2,14 @@
 //
 //   k_ghost_all   one launch over the padded box: outflow / periodic / fixed
 //                 ghost points of the stage primitives, E and face fields
-//   k_sweep<D>    LDS-staged sweep along direction D: per-cell reconstruction
-//                 of the ten face variables, HLL flux on every D-face
-//   k_face_E      covariant E_k at the a-faces of edge direction k
-//   k_edge_emf    upwind constrained-transport EMF on the edges
+//   k_xy          x and y phases of the explicit operator on an LDS-staged
+//                 tile: reconstruction of the ten face variables, HLL flux
+//                 on every face, flux divergence
+//   k_ct          upwind constrained-transport EMF on the edges
 //   k_face_update CT update of the face fields + stage accumulation
-//   k_cell_update flux divergence, Cowling sources, stage accumulation, fused
-//                 implicit E + velocity Newton solve or final recovery
+//   k_cell_update z phase of the explicit operator (3-D), Cowling sources,
+//                 stage accumulation, fused implicit E + velocity Newton
+//                 solve or final recovery
 // Paper: Cheong et al., arXiv:2110.03732, Sec 2.1-2.6 and Sec 3.2.
 #pragma once
 #include "common.h"
@@ -99,22 +100,33 @@ __device__ __forceinline__ void hll_face(const Phys &P, const double sL[10], con
     constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
     double ps2 = MET ? ps * ps : 1.0;
     if (MET) bn *= frcp(ps2 * ps2 * ps2);
-    double uL[3], uR[3], EL[3], ER[3], BL[3], BR[3];
+    double h[8];
 #pragma unroll
-    for (int i = 0; i < 3; i++) {
-        uL[i] = ps2 * sL[1 + i];
-        uR[i] = ps2 * sR[1 + i];
-        EL[i] = ps2 * sL[5 + i];
-        ER[i] = ps2 * sR[5 + i];
+    for (int v = 0; v < 8; v++) h[v] = 0.0;
+    {
+        double u[3], E[3], B[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            u[i] = ps2 * sL[1 + i];
+            E[i] = ps2 * sL[5 + i];
+        }
+        B[D] = ps2 * bn;
+        B[t1] = ps2 * sL[8];
+        B[t2] = ps2 * sL[9];
+        hll_accumulate<D>(P, sL[0], u, sL[4], E, B, 1.0, h);
     }
-    BL[D] = BR[D] = ps2 * bn;
-    BL[t1] = ps2 * sL[8];
-    BR[t1] = ps2 * sR[8];
-    BL[t2] = ps2 * sL[9];
-    BR[t2] = ps2 * sR[9];
-    double qL[8], qR[8], gL[8], gR[8];
-    flat_cons_flux(P, D, sL[0], uL, sL[4], EL, BL, qL, gL);
-    flat_cons_flux(P, D, sR[0], uR, sR[4], ER, BR, qR, gR);
+    {
+        double u[3], E[3], B[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            u[i] = ps2 * sR[1 + i];
+            E[i] = ps2 * sR[5 + i];
+        }
+        B[D] = ps2 * bn;
+        B[t1] = ps2 * sR[8];
+        B[t2] = ps2 * sR[9];
+        hll_accumulate<D>(P, sR[0], u, sR[4], E, B, -1.0, h);
+    }
     double sD = 1.0, sS = 1.0, sE = 1.0;
     if (MET) {
         double p4 = ps2 * ps2;
@@ -124,9 +136,8 @@ __device__ __forceinline__ void hll_face(const Phys &P, const double sL[10], con
     }
 #pragma unroll
     for (int v = 0; v < 8; v++) {
-        double h = 0.5 * (gL[v] + gR[v]) - 0.5 * (qR[v] - qL[v]);
         double sc = (v == 0 || v == 4) ? sD : (v < 4 ? sS : sE);
-        Fout[v] = sc * h;
+        Fout[v] = sc * h[v];
     }
 }
 
@@ -153,121 +164,142 @@ __device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const C
     return b;
 }
 
-// LDS-staged sweep along D.  Tile: TX x TY x TZ cells (one per thread), with a
-// halo of 3 cells along D.  Every thread forms the HLL flux on the lower
-// D-face of its cell from the six-cell windows in LDS; the upper boundary
-// face of each line is done by k_last_face.
-template <int D>
-struct Tile;
-template <>
-struct Tile<0> {
-    static constexpr int TX = 64, TY = 4, TZ = 1;
-};
-template <>
-struct Tile<1> {
-    static constexpr int TX = 16, TY = 16, TZ = 1;
-};
-template <>
-struct Tile<2> {
-    static constexpr int TX = 16, TY = 1, TZ = 16;
+// One directional phase of the explicit operator over a tile of cells
+// [org, org + T), T = (T0, T1, T2) with one thread per cell: the tile plus a
+// 3-cell halo along D of the ten face variables goes to LDS; the T_D + 1 faces
+// of every line get the HLL flux (a thread takes face tid and, for the few
+// faces beyond one per thread, face tid + NT); the fluxes are exchanged
+// through the same LDS and each thread returns minus the flux difference of
+// its cell divided by dx_D.  Coordinates are clamped into the padded array;
+// results for points beyond the interior are computed but never stored.
+template <int D, int T0, int T1, int T2>
+struct PhaseDims {
+    static constexpr int NT = T0 * T1 * T2;
+    static constexpr int H = 3;
+    static constexpr int E0 = T0 + (D == 0 ? 2 * H : 0), E1 = T1 + (D == 1 ? 2 * H : 0),
+                         E2 = T2 + (D == 2 ? 2 * H : 0);
+    static constexpr int NRAW = E0 * E1 * E2;
+    static constexpr int SD = D == 0 ? 1 : (D == 1 ? E0 : E0 * E1);
+    static constexpr int F0 = T0 + (D == 0), F1 = T1 + (D == 1), F2 = T2 + (D == 2);
+    static constexpr int NF = F0 * F1 * F2;
+    static constexpr int FS = D == 0 ? 1 : (D == 1 ? F0 : F0 * F1);
+    static constexpr int NV = 10;
+    static constexpr int LDS = NV * NRAW;  // doubles
+    static_assert(NF <= 2 * NT, "at most two faces per thread");
+    static_assert(8 * NF <= NV * NRAW, "fluxes fit in the staging buffer");
 };
 
-template <int REC, int MET, int D>
-__global__ void __launch_bounds__(kBlock) k_sweep(Geo G, Phys P, CPtr<8> sp, CPtr<3> sf, CPtr<2> met, Ptr<8> F)
+template <int REC, int MET, int D, int T0, int T1, int T2>
+__device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const CPtr<8> &sp, const CPtr<3> &sf,
+                                            const CPtr<2> &met, const int org[3], double *lds, double Ld[8])
 {
-    constexpr int TX = Tile<D>::TX, TY = Tile<D>::TY, TZ = Tile<D>::TZ;
-    constexpr int HX = (D == 0) ? 3 : 0, HY = (D == 1) ? 3 : 0, HZ = (D == 2) ? 3 : 0;
-    constexpr int EX = TX + 2 * HX, EY = TY + 2 * HY;
-    constexpr int NRAW = EX * EY * (TZ + 2 * HZ);
-    constexpr int NV = 10 + 2 * MET;
+    using PD = PhaseDims<D, T0, T1, T2>;
+    constexpr int NT = PD::NT, H = PD::H, E0 = PD::E0, E1 = PD::E1, NRAW = PD::NRAW, SD = PD::SD;
+    constexpr int F0 = PD::F0, F1 = PD::F1, NF = PD::NF;
     constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
-    constexpr int SD = (D == 0) ? 1 : (D == 1 ? EX : EX * EY);  // LDS stride along D
-
-    __shared__ double raw[NV][NRAW];
-
+    double(*raw)[NRAW] = reinterpret_cast<double(*)[NRAW]>(lds);
     const int tid = threadIdx.x;
-    const int ox = G.g[0] + blockIdx.x * TX, oy = G.g[1] + blockIdx.y * TY, oz = G.g[2] + blockIdx.z * TZ;
 
-    // ---- tile + halo of every variable into LDS (clamped at the array ends)
-    for (int l = tid; l < NRAW; l += kBlock) {
-        int lx = l % EX, ly = (l / EX) % EY, lz = l / (EX * EY);
-        int c[3] = {ox + lx - HX, oy + ly - HY, oz + lz - HZ};
+    // every load of the staging rounds is issued before the first LDS store
+    constexpr int NR = (NRAW + NT - 1) / NT;
+    double st[NR][10];
 #pragma unroll
-        for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
-        unsigned o = (unsigned)lin(G, c) << 3;
+    for (int k = 0; k < NR; k++) {
+        const int l = tid + k * NT;
+        if (l < NRAW) {
+            int c[3] = {org[0] + l % E0, org[1] + (l / E0) % E1, org[2] + l / (E0 * E1)};
+            c[D] -= H;
 #pragma unroll
-        for (int v = 0; v < 8; v++) raw[v][l] = ldb(sp.p[v], o);
-        raw[8][l] = bcc_t<MET>(G, sf, met, c, t1);
-        raw[9][l] = bcc_t<MET>(G, sf, met, c, t2);
-        if (MET) {
-            raw[10][l] = ldb(met.p[0], o);
-            raw[10 + MET][l] = ldb(met.p[1], o);
+            for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
+            unsigned o = (unsigned)lin(G, c) << 3;
+#pragma unroll
+            for (int v = 0; v < 8; v++) st[k][v] = ldb(sp.p[v], o);
+            st[k][8] = bcc_t<MET>(G, sf, met, c, t1);
+            st[k][9] = bcc_t<MET>(G, sf, met, c, t2);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; k++) {
+        const int l = tid + k * NT;
+        if (l < NRAW) {
+#pragma unroll
+            for (int v = 0; v < 10; v++) raw[v][l] = st[k][v];
         }
     }
     __syncthreads();
 
-    // ---- flux on the lower D-face of this thread's cell
-    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    int c[3] = {ox + lx, oy + ly, oz + lz};
-    if (c[0] >= G.g[0] + G.n[0] || c[1] >= G.g[1] + G.n[1] || c[2] >= G.g[2] + G.n[2]) return;
-    const int r0 = ((lz + HZ) * EY + (ly + HY)) * EX + (lx + HX);  // LDS index of the cell
-    double sL[10], sR[10];
+    double Fr[2][8];
 #pragma unroll
-    for (int v = 0; v < 10; v++) {
-        double w[6];
+    for (int k = 0; k < 2; k++) {
+        const int f = tid + k * NT;
+        if (k == 1 && f >= NF) break;
+        int e[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
+        const int r0 = (e[0] + (D == 0 ? H : 0)) + E0 * ((e[1] + (D == 1 ? H : 0)) + E1 * (e[2] + (D == 2 ? H : 0)));
+        double sL[10], sR[10];
 #pragma unroll
-        for (int m = 0; m < 6; m++) w[m] = raw[v][r0 + (m - 3) * SD];
-        recon_face<REC>(w, sL[v], sR[v]);
+        for (int v = 0; v < 10; v++) {
+            double w[6];
+#pragma unroll
+            for (int m = 0; m < 6; m++) w[m] = raw[v][r0 + (m - 3) * SD];
+            recon_face<REC>(w, sL[v], sR[v]);
+        }
+        int c[3] = {org[0] + e[0], org[1] + e[1], org[2] + e[2]};
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            int lo = (d == D) ? 1 : 0;
+            c[d] = c[d] < lo ? lo : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
+        }
+        const unsigned o = (unsigned)lin(G, c) << 3;
+        double al = 1.0, ps = 1.0;
+        if (MET) {
+            const unsigned om = o - ((unsigned)G.st[D] << 3);
+            al = 0.5 * (ldb(met.p[0], om) + ldb(met.p[0], o));
+            ps = 0.5 * (ldb(met.p[1], om) + ldb(met.p[1], o));
+        }
+        hll_face<MET, D>(P, sL, sR, al, ps, ldb(sf.p[D], o), Fr[k]);
     }
-    double al = 1.0, ps = 1.0;
-    if (MET) {
-        al = 0.5 * (raw[10][r0 - SD] + raw[10][r0]);
-        ps = 0.5 * (raw[10 + MET][r0 - SD] + raw[10 + MET][r0]);
-    }
-    unsigned o = (unsigned)lin(G, c) << 3;
-    double Fo[8];
-    hll_face<MET, D>(P, sL, sR, al, ps, ldb(sf.p[D], o), Fo);
+    __syncthreads();
+    double(*fl)[NF] = reinterpret_cast<double(*)[NF]>(lds);
 #pragma unroll
-    for (int v = 0; v < 8; v++) stb(F.p[v], o, Fo[v]);
+    for (int k = 0; k < 2; k++) {
+        const int f = tid + k * NT;
+        if (k == 1 && f >= NF) break;
+#pragma unroll
+        for (int v = 0; v < 8; v++) fl[v][f] = Fr[k][v];
+    }
+    __syncthreads();
+    const int f0 = (tid % T0) + F0 * (((tid / T0) % T1) + F1 * (tid / (T0 * T1)));
+#pragma unroll
+    for (int v = 0; v < 8; v++) Ld[v] = -(fl[v][f0 + PD::FS] - fl[v][f0]) * G.idx[D];
+    __syncthreads();  // the buffer is free for the next phase
 }
 
-// the upper boundary D-face (index g + n) of every line, from global memory
-template <int REC, int MET, int D>
-__global__ void __launch_bounds__(kBlock) k_last_face(Geo G, Phys P, Region R, CPtr<8> sp, CPtr<3> sf, CPtr<2> met,
-                                                      Ptr<8> F)
+// x and y phases of the explicit operator on a TX x TY tile of one z plane:
+// Lxy = -(dF_x/dx) - (dF_y/dy) of every interior cell (the y phase only where
+// y is active)
+template <int REC, int MET, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_xy(Geo G, Phys P, CPtr<8> sp, CPtr<3> sf, CPtr<2> met, Ptr<8> Lxy)
 {
-    constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
-    int c[3];
-    if (!region_point(R, c)) return;
-    int id = lin(G, c);
-    int s = G.st[D];
-    double sL[10], sR[10];
+    constexpr int LX = PhaseDims<0, TX, TY, 1>::LDS, LY = PhaseDims<1, TX, TY, 1>::LDS;
+    __shared__ double lds[LX > LY ? LX : LY];
+    unsigned bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int org[3] = {G.g[0] + (int)bx * TX, G.g[1] + (int)by * TY, G.g[2] + (int)bz};
+    double L[8];
+    sweep_phase<REC, MET, 0, TX, TY, 1>(G, P, sp, sf, met, org, lds, L);
+    if (G.act[1]) {
+        double Ly[8];
+        sweep_phase<REC, MET, 1, TX, TY, 1>(G, P, sp, sf, met, org, lds, Ly);
 #pragma unroll
-    for (int v = 0; v < 8; v++) recon_at<REC>(sp.p[v], id, s, sL[v], sR[v]);
-    double w1[6], w2[6];
-#pragma unroll
-    for (int m = 0; m < 6; m++) {
-        int cc[3] = {c[0], c[1], c[2]};
-        cc[D] += m - 3;
-        if (REC != GR_PPM && (m == 0 || m == 5)) cc[D] += (m == 0) ? 1 : -1;
-        w1[m] = bcc_t<MET>(G, sf, met, cc, t1);
-        w2[m] = bcc_t<MET>(G, sf, met, cc, t2);
+        for (int v = 0; v < 8; v++) L[v] += Ly[v];
     }
-    recon_face<REC>(w1, sL[8], sR[8]);
-    recon_face<REC>(w2, sL[9], sR[9]);
-    double al = 1.0, ps = 1.0;
-    if (MET) {
-        al = 0.5 * (met.p[0][id - s] + met.p[0][id]);
-        ps = 0.5 * (met.p[1][id - s] + met.p[1][id]);
-    }
-    double Fo[8];
-    hll_face<MET, D>(P, sL, sR, al, ps, sf.p[D][id], Fo);
+    const int c[3] = {org[0] + (int)threadIdx.x % TX, org[1] + (int)threadIdx.x / TX, org[2]};
+    if (c[0] >= G.g[0] + G.n[0] || c[1] >= G.g[1] + G.n[1]) return;
+    const unsigned o = (unsigned)lin(G, c) << 3;
 #pragma unroll
-    for (int v = 0; v < 8; v++) F.p[v][id] = Fo[v];
+    for (int v = 0; v < 8; v++) stb(Lxy.p[v], o, L[v]);
 }
 
-// ---------------------------------------------------------------------------
-// metric of the face of direction d at index id (mean of the two cells)
 template <int MET>
 __device__ __forceinline__ void face_metric(const Geo &G, const CPtr<2> &met, unsigned o, int d, double &al,
                                             double &ps)
@@ -287,83 +319,134 @@ __device__ __forceinline__ void face_metric(const Geo &G, const CPtr<2> &met, un
     ps = 0.5 * (ldb(met.p[1], om) + ldb(met.p[1], o));
 }
 
-// covariant E_k = psi^4 E^k at the a-faces of edge direction k, left and right
-// states of the reconstruction along a (Sec 3.2 steps (ii)-(iii))
-template <int REC, int MET>
-__global__ void __launch_bounds__(kBlock) k_face_E(Geo G, int k, Region R, const double *__restrict__ Ek, CPtr<2> met,
-                                                   double *__restrict__ EfL, double *__restrict__ EfR)
-{
-    int c[3];
-    if (!region_point(R, c)) return;
-    int a = (k + 1) % 3;
-    int id = lin(G, c);
-    unsigned o = (unsigned)id << 3;
-    double al, ps;
-    face_metric<MET>(G, met, o, a, al, ps);
-    double p4 = MET ? ps * ps * ps * ps : 1.0;
-    double L, Rv;
-    if (G.act[a]) {
-        recon_at<REC>(Ek, id, G.st[a], L, Rv);
-    } else {
-        L = Rv = ldb(Ek, o);
-    }
-    stb(EfL, o, p4 * L);
-    stb(EfR, o, p4 * Rv);
-}
+// Upwind constrained-transport EMF hat-E_k on the k-edges (Sec 3.2), (k, a, b)
+// cyclic.  One block owns a tile of edges.  Step 1 forms, for every a-face the
+// tile needs (its edges' a-index, b widened by the reconstruction halo), the
+// left/right states of the covariant E_k = psi^4 E^k reconstructed along a and
+// the normal face field q_B^a; they go to LDS.  Step 2 reconstructs those
+// along b to the edge (the LL, LR, RL, RR states), reconstructs q_B^b along a,
+// and combines them with the metric-only speeds (c+ = c-).
+template <int K>
+struct CtTile;
+template <>
+struct CtTile<2> {  // z-edges: a = x, b = y
+    static constexpr int T[3] = {32, 8, 1};
+};
+template <>
+struct CtTile<1> {  // y-edges: a = z, b = x
+    static constexpr int T[3] = {32, 1, 8};
+};
+template <>
+struct CtTile<0> {  // x-edges: a = y, b = z
+    static constexpr int T[3] = {16, 4, 4};
+};
 
-// upwind EMF hat-E_k on the edges (Sec 3.2 steps (iv)-(vii)), (k, a, b) cyclic
-template <int REC, int MET>
-__global__ void __launch_bounds__(kBlock) k_edge_emf(Geo G, int k, Region R, CPtr<3> sf, CPtr<2> met,
-                                                     const double *__restrict__ EfL, const double *__restrict__ EfR,
-                                                     double *__restrict__ EM)
+template <int REC, int MET, int K>
+__global__ void __launch_bounds__(kBlock) k_ct(Geo G, Region R, const double *__restrict__ Ek, CPtr<3> sf, CPtr<2> met,
+                                              double *__restrict__ EM)
 {
-    int c[3];
-    if (!region_point(R, c)) return;
-    int a = (k + 1) % 3, b = (k + 2) % 3;
-    int id = lin(G, c);
-    unsigned o = (unsigned)id << 3;
-    double ELL, ELR, ERL, ERR, qbL, qbR, qaL, qaR;
-    if (G.act[b]) {
-        recon_at<REC>(EfL, id, G.st[b], ELL, ELR);
-        recon_at<REC>(EfR, id, G.st[b], ERL, ERR);
-        recon_at<REC>(sf.p[a], id, G.st[b], qaL, qaR);
-    } else {
-        ELL = ELR = ldb(EfL, o);
-        ERL = ERR = ldb(EfR, o);
-        qaL = qaR = ldb(sf.p[a], o);
+    constexpr int A = (K + 1) % 3, B = (K + 2) % 3;
+    constexpr int T0 = CtTile<K>::T[0], T1 = CtTile<K>::T[1], T2 = CtTile<K>::T[2];
+    constexpr int HB = 3;
+    constexpr int E0 = T0 + (B == 0 ? 2 * HB : 0), E1 = T1 + (B == 1 ? 2 * HB : 0), E2 = T2 + (B == 2 ? 2 * HB : 0);
+    constexpr int NL = E0 * E1 * E2;
+    constexpr int SB = (B == 0) ? 1 : (B == 1 ? E0 : E0 * E1);  // LDS stride along b
+    static_assert(T0 * T1 * T2 == kBlock, "one edge per thread");
+    __shared__ double sEL[NL], sER[NL], sQa[NL];
+
+    const int tid = threadIdx.x;
+    unsigned bx, by, bz;
+    xcd_block(bx, by, bz);
+    const int org[3] = {R.lo[0] + (int)bx * T0, R.lo[1] + (int)by * T1, R.lo[2] + (int)bz * T2};
+    const bool actA = G.act[A], actB = G.act[B];
+
+    // ---- step 1: a-face states of psi^4 E_k and q_B^a, clamped into range
+    for (int l = tid; l < NL; l += kBlock) {
+        int e[3] = {l % E0, (l / E0) % E1, l / (E0 * E1)};
+        int c[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            int lo = R.lo[d], hi = R.lo[d] + R.cnt[d] - 1;
+            c[d] = org[d] + e[d];
+            if (d == B) {
+                c[d] -= HB;
+                lo = lo - HB < 0 ? 0 : lo - HB;
+                hi = hi + HB > G.N[d] - 1 ? G.N[d] - 1 : hi + HB;
+            }
+            c[d] = c[d] < lo ? lo : (c[d] > hi ? hi : c[d]);
+        }
+        int id = lin(G, c);
+        unsigned o = (unsigned)id << 3;
+        double al, ps;
+        face_metric<MET>(G, met, o, A, al, ps);
+        double p4 = MET ? ps * ps * ps * ps : 1.0;
+        double L, Rv;
+        if (actA) {
+            recon_at<REC>(Ek, id, G.st[A], L, Rv);
+        } else {
+            L = Rv = ldb(Ek, o);
+        }
+        sEL[l] = p4 * L;
+        sER[l] = p4 * Rv;
+        sQa[l] = ldb(sf.p[A], o);
     }
-    if (G.act[a]) {
-        recon_at<REC>(sf.p[b], id, G.st[a], qbL, qbR);
+    __syncthreads();
+
+    // ---- step 2: this thread's edge
+    const int t[3] = {tid % T0, (tid / T0) % T1, tid / (T0 * T1)};
+    int c[3] = {org[0] + t[0], org[1] + t[1], org[2] + t[2]};
+    if (c[0] >= R.lo[0] + R.cnt[0] || c[1] >= R.lo[1] + R.cnt[1] || c[2] >= R.lo[2] + R.cnt[2]) return;
+    const int r0 = t[0] + (B == 0 ? HB : 0) + E0 * (t[1] + (B == 1 ? HB : 0) + E1 * (t[2] + (B == 2 ? HB : 0)));
+    double ELL, ELR, ERL, ERR, qaL, qaR, qbL, qbR;
+    if (actB) {
+        double w[6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sEL[r0 + (m - 3) * SB];
+        recon_face<REC>(w, ELL, ELR);
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sER[r0 + (m - 3) * SB];
+        recon_face<REC>(w, ERL, ERR);
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sQa[r0 + (m - 3) * SB];
+        recon_face<REC>(w, qaL, qaR);
     } else {
-        qbL = qbR = ldb(sf.p[b], o);
+        ELL = ELR = sEL[r0];
+        ERL = ERR = sER[r0];
+        qaL = qaR = sQa[r0];
+    }
+    const int id = lin(G, c);
+    const unsigned o = (unsigned)id << 3;
+    if (actA) {
+        recon_at<REC>(sf.p[B], id, G.st[A], qbL, qbR);
+    } else {
+        qbL = qbR = ldb(sf.p[B], o);
     }
     double ca = 1.0, cb = 1.0, ae = 1.0;
     if (MET) {
-        unsigned sa = G.act[a] ? ((unsigned)G.st[a] << 3) : 0u, sbb = G.act[b] ? ((unsigned)G.st[b] << 3) : 0u;
+        unsigned sa = actA ? ((unsigned)G.st[A] << 3) : 0u, sbb = actB ? ((unsigned)G.st[B] << 3) : 0u;
         double al0, ps0, al1, ps1;
-        face_metric<MET>(G, met, o - sbb, a, al0, ps0);
-        face_metric<MET>(G, met, o, a, al1, ps1);
+        face_metric<MET>(G, met, o - sbb, A, al0, ps0);
+        face_metric<MET>(G, met, o, A, al1, ps1);
         ca = fmax(al0 * frcp(ps0 * ps0), al1 * frcp(ps1 * ps1));
-        face_metric<MET>(G, met, o - sa, b, al0, ps0);
-        face_metric<MET>(G, met, o, b, al1, ps1);
+        face_metric<MET>(G, met, o - sa, B, al0, ps0);
+        face_metric<MET>(G, met, o, B, al1, ps1);
         cb = fmax(al0 * frcp(ps0 * ps0), al1 * frcp(ps1 * ps1));
         double sm = ldb(met.p[0], o);
         int na = 1;
-        if (G.act[a]) {
+        if (actA) {
             sm += ldb(met.p[0], o - sa);
             na++;
         }
-        if (G.act[b]) {
+        if (actB) {
             sm += ldb(met.p[0], o - sbb);
             na++;
         }
-        if (G.act[a] && G.act[b]) {
+        if (actA && actB) {
             sm += ldb(met.p[0], o - sa - sbb);
             na++;
         }
         ae = sm / na;
     }
-    // metric-only speeds: c+ = c- in every direction
     stb(EM, o, ae * 0.25 * (ELL + ELR + ERL + ERR) + 0.5 * ca * (qbR - qbL) - 0.5 * cb * (qaR - qaL));
 }
 
@@ -374,39 +457,49 @@ struct StageArgs {
     double cL[4], cR[4];  // weights of L_j and R_j (j < p); final pass: wt, w
 };
 
-// CT update of the face fields of direction d (eq. ct):
-// Lf = -(d_{m1} E_{m2} - d_{m2} E_{m1}); stage face = face^n + dt sum_j cL_j Lf_j
+// CT update of the face fields (eq. ct), all three directions in one pass:
+// Lf_d = -(d_{m1} E_{m2} - d_{m2} E_{m1}); stage face = face^n + dt sum_j cL_j Lf_j.
+// The region is the interior plus one layer in every active direction; face d
+// exists at c when c lies inside the interior in the other two directions.
 struct FaceLs {
-    const double *Lf[4];  // stored face L of stages j (direction d), may be null
+    const double *Lf[4][3];  // stored face L of stage j, direction d (may be null)
+    double *Lst[3];          // where this pass stores its face L (withL)
 };
-__global__ void __launch_bounds__(kBlock) k_face_update(Geo G, int d, Region R, StageArgs A, CPtr<3> EM,
-                                                        const double *fn, FaceLs Ls, double *Lstore, double *fout)
+__global__ void __launch_bounds__(kBlock) k_face_update(Geo G, Region R, StageArgs A, CPtr<3> EM, CPtr<3> fn,
+                                                        FaceLs Ls, Ptr<3> fout)
 {
     int c[3];
     if (!region_point(R, c)) return;
-    int m1 = (d + 1) % 3, m2 = (d + 2) % 3;
-    unsigned o = (unsigned)lin(G, c) << 3;
-    double acc = ldb(fn, o);
-    double Lnew = 0.0;
-    if (A.withL) {
-        double t1 = G.act[m1] ? (ldb(EM.p[m2], o + ((unsigned)G.st[m1] << 3)) - ldb(EM.p[m2], o)) * G.idx[m1] : 0.0;
-        double t2 = G.act[m2] ? (ldb(EM.p[m1], o + ((unsigned)G.st[m2] << 3)) - ldb(EM.p[m1], o)) * G.idx[m2] : 0.0;
-        Lnew = -(t1 - t2);
-        if (A.storeL) stb(Lstore, o, Lnew);
-    }
+    bool in[3];
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        if (j >= A.p || A.cL[j] == 0.0) continue;
-        double l = (A.withL && j == A.p - 1) ? Lnew : ldb(Ls.Lf[j], o);
-        acc += A.dt * A.cL[j] * l;
+    for (int d = 0; d < 3; d++) in[d] = c[d] < G.g[d] + G.n[d];
+    const unsigned o = (unsigned)lin(G, c) << 3;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int m1 = (d + 1) % 3, m2 = (d + 2) % 3;
+        if (!in[m1] || !in[m2]) continue;
+        double acc = ldb(fn.p[d], o);
+        double Lnew = 0.0;
+        if (A.withL) {
+            double t1 = G.act[m1] ? (ldb(EM.p[m2], o + ((unsigned)G.st[m1] << 3)) - ldb(EM.p[m2], o)) * G.idx[m1] : 0.0;
+            double t2 = G.act[m2] ? (ldb(EM.p[m1], o + ((unsigned)G.st[m2] << 3)) - ldb(EM.p[m1], o)) * G.idx[m2] : 0.0;
+            Lnew = -(t1 - t2);
+            if (A.storeL) stb(Ls.Lst[d], o, Lnew);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (j >= A.p || A.cL[j] == 0.0) continue;
+            double l = (A.withL && j == A.p - 1) ? Lnew : ldb(Ls.Lf[j][d], o);
+            acc += A.dt * A.cL[j] * l;
+        }
+        stb(fout.p[d], o, acc);
     }
-    stb(fout, o, acc);
 }
 
 // ---------------------------------------------------------------------------
 // cell pass
 struct CellIO {
-    const double *F[3][8];   // fluxes of the three directions (if withL)
+    const double *Lxy[8];    // -(dF_x/dx + dF_y/dy) of stage p-1 (if withL)
     const double *spm[8];    // stage p-1 primitives + E (if withL)
     const double *sfm[3];    // stage p-1 faces (if withL)
     const double *Lc[4][8];  // stored cell L of stages j < p
@@ -428,11 +521,36 @@ __device__ __forceinline__ double bcc_dev(const Geo &G, const double *const *fac
     return MET ? v * ip6 : v;
 }
 
-template <int MET>
+// cell pass.  SWZ: the z phase of the explicit operator runs first on a
+// TX x 1 x TZ tile (one thread per cell), the other variants take one cell per
+// thread over the interior.
+template <int REC, int MET, int SWZ, int TX, int TZ>
 __global__ void __launch_bounds__(kBlock) k_cell_update(Geo G, Phys P, Region R, StageArgs A, CellIO io)
 {
     int c[3];
-    if (!region_point(R, c)) return;
+    double Lz[8];
+    if (SWZ) {
+        __shared__ double lds[SWZ ? PhaseDims<2, TX, 1, TZ>::LDS : 1];
+        unsigned bx, by, bz;
+        xcd_block(bx, by, bz);
+        const int org[3] = {R.lo[0] + (int)bx * TX, R.lo[1] + (int)by, R.lo[2] + (int)bz * TZ};
+        CPtr<8> sp;
+        CPtr<3> sf;
+        CPtr<2> met;
+#pragma unroll
+        for (int v = 0; v < 8; v++) sp.p[v] = io.spm[v];
+#pragma unroll
+        for (int d = 0; d < 3; d++) sf.p[d] = io.sfm[d];
+        met.p[0] = io.met[0];
+        met.p[1] = io.met[1];
+        sweep_phase<REC, MET, 2, TX, 1, TZ>(G, P, sp, sf, met, org, lds, Lz);
+        c[0] = org[0] + (int)threadIdx.x % TX;
+        c[1] = org[1];
+        c[2] = org[2] + (int)threadIdx.x / TX;
+        if (c[0] >= R.lo[0] + R.cnt[0] || c[2] >= R.lo[2] + R.cnt[2]) return;
+    } else {
+        if (!region_point(R, c)) return;
+    }
     const unsigned o = (unsigned)lin(G, c) << 3;
     double al = 1.0, ps = 1.0;
     if (MET) {
@@ -444,14 +562,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_update(Geo G, Phys P, Region R,
     double Lc[8];
     if (A.withL) {
 #pragma unroll
-        for (int v = 0; v < 8; v++) Lc[v] = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            if (!G.act[d]) continue;
-            unsigned op = o + ((unsigned)G.st[d] << 3);
-#pragma unroll
-            for (int v = 0; v < 8; v++) Lc[v] -= (ldb(io.F[d][v], op) - ldb(io.F[d][v], o)) * G.idx[d];
-        }
+        for (int v = 0; v < 8; v++) Lc[v] = SWZ ? ldb(io.Lxy[v], o) + Lz[v] : ldb(io.Lxy[v], o);
         double rho = ldb(io.spm[0], o), pr = ldb(io.spm[4], o);
         double u[3] = {ps2 * ldb(io.spm[1], o), ps2 * ldb(io.spm[2], o), ps2 * ldb(io.spm[3], o)};
         double W = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
