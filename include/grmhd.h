@@ -162,6 +162,60 @@ gr_status gr_timing_read(int kernel_class, double *total_ms, long *launches, dou
 /* Name of a kernel class ("" when out of range). */
 const char *gr_kernel_class_name(int kernel_class);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent runs (not a construct of the paper: the same step
+ * of Sec 2.3 applied to many grids at once).
+ *
+ * A batch advances nruns independent runs -- any mix of sizes, dimensions,
+ * reconstructions, metrics and resistivities, all with the same IMEX
+ * tableau -- by one full step each per call.  Every kernel launch of a step
+ * serves all runs that share its template instance: its grid concatenates
+ * the runs' block ranges, and each block finds its run through a prefix
+ * array.  The batch copies grids, state descriptors and time steps; the
+ * arrays they point to stay owned by the caller and must outlive the batch.
+ * The batch owns one device block of kernel arguments and, after the first
+ * gr_batch_run, one captured HIP graph of a step.  Results of a run do not
+ * depend on the other runs of the batch: every cell of a run is computed by
+ * the same arithmetic as in gr_step.
+ */
+typedef struct gr_batch gr_batch;
+
+/* Build a batch.  dt: one time step per run (host array).  tune_cache: NULL
+ * keeps the default tiles; "" times the tile candidates of every class of
+ * runs (recon, metric, ndim) on these runs and keeps the fastest; a path
+ * does the same for the classes not yet listed in that text file and
+ * appends its decisions to it.  Allocates the argument block (hipMalloc) and
+ * synchronises the stream.  GR_EUNSUPPORTED if the runs mix IMEX tableaux. */
+gr_status gr_batch_create(gr_batch **batch, const gr_grid *grids, const gr_state *states, const double *dt,
+                          int nruns, const char *tune_cache, hipStream_t stream);
+
+/* Replace the time steps (host array of nruns); synchronises the stream and
+ * rebuilds the argument block (a later gr_batch_run captures a new graph). */
+gr_status gr_batch_set_dt(gr_batch *batch, const double *dt, hipStream_t stream);
+
+/* One step of every run, launched eagerly on the stream. */
+gr_status gr_batch_step(gr_batch *batch, hipStream_t stream);
+
+/* nsteps steps of every run: on the first call the step is captured into a
+ * HIP graph (on a capture stream the batch creates; the launches are never
+ * executed there) and the graph is then launched nsteps times on the given
+ * stream, which may be the null stream.  Asynchronous. */
+gr_status gr_batch_run(gr_batch *batch, int nsteps, hipStream_t stream);
+
+/* Launches per step, algorithmic bytes per step (summed over runs, same
+ * count as the measurement hook), interior cells summed over runs. */
+gr_status gr_batch_stats(const gr_batch *batch, int *launches_per_step, double *alg_bytes_per_step,
+                         long *cells);
+
+/* Tiles chosen for one run: x/y-phase tile and z-phase tile indices, named
+ * by gr_tile_name(0, xy) and gr_tile_name(1, cz). */
+gr_status gr_batch_tiles(const gr_batch *batch, int run, int *xy_tile, int *cz_tile);
+const char *gr_tile_name(int which, int tile);
+
+/* Free the batch (argument block and graph).  Does not synchronise: the
+ * caller makes sure no launch of the batch is still pending. */
+gr_status gr_batch_destroy(gr_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) k_init_cons(Geo G, Phys P, Region R, CPtr
                                                    CPtr<2> met, Ptr<8> q)
 {
     int c[3];
-    if (!region_point(R, c)) return;
+    if (!region_point(R, Blk{blockIdx.x, blockIdx.y, blockIdx.z}, c)) return;
     int id = lin(G, c);
     double ps = MET ? met.p[1][id] : 1.0;
     double ps2 = ps * ps, ps6 = ps2 * ps2 * ps2;

@@ -31,38 +31,69 @@ struct Region {
     int lo[3], cnt[3];
 };
 
+// Block coordinates.  A kernel body sees its block as Blk inside a grid of
+// GridDims.  For a plain launch these are the hardware ids; for a batched
+// launch (one 1-D grid over the concatenated block ranges of many runs) the
+// body sees the block's position inside its own run's grid.
+struct GridDims {
+    unsigned x, y, z;
+};
+struct Blk {
+    unsigned x, y, z;
+};
+
 // XCD-aware block order.  Workgroups are dealt round-robin to the 8 XCDs
 // (dispatch id i runs on XCD i mod 8), each with its own L2.  Renumbering so
 // that XCD x receives the contiguous run [x P, (x + 1) P) of logical blocks
 // keeps stencil neighbours (adjacent rows, planes and tiles) in one L2.  The
 // tail of a grid that does not divide by 8 keeps its order.
 constexpr int kXcd = 8;
-__device__ __forceinline__ void xcd_block(unsigned &bx, unsigned &by, unsigned &bz)
+template <bool XCD>
+__device__ __forceinline__ unsigned hw_linear()
 {
     unsigned gx = gridDim.x, gy = gridDim.y;
-    unsigned total = gx * gy * gridDim.z;
     unsigned L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    unsigned per = total / kXcd;
-    if (L < per * kXcd) L = (L % kXcd) * per + L / kXcd;
-    bx = L % gx;
-    unsigned r = L / gx;
-    by = r % gy;
-    bz = r / gy;
+    if (XCD) {
+        unsigned total = gx * gy * gridDim.z;
+        unsigned per = total / kXcd;
+        if (L < per * kXcd) L = (L % kXcd) * per + L / kXcd;
+    }
+    return L;
+}
+__device__ __forceinline__ Blk blk_of(unsigned L, const GridDims &g)
+{
+    Blk b;
+    b.x = L % g.x;
+    unsigned r = L / g.x;
+    b.y = r % g.y;
+    b.z = r / g.y;
+    return b;
+}
+// batched launch: start[r] is the first block of run r (start[n] = total);
+// returns the run of this block and its linear index inside that run's grid
+template <bool XCD>
+__device__ __forceinline__ int batch_locate(const unsigned *__restrict__ start, int n, unsigned &local)
+{
+    unsigned L = hw_linear<XCD>();
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= L) lo = mid;
+        else hi = mid - 1;
+    }
+    local = L - start[lo];
+    return lo;
 }
 
-// XCD: renumber blocks for kernels that read stencils; streaming kernels keep
-// the dispatch order
-template <bool XCD = false>
-__device__ __forceinline__ bool region_point(const Region &R, int c[3])
+// flat kernels: 1-D blocks run over the (x, y) plane of a region, Blk.y over z
+__device__ __forceinline__ bool region_point(const Region &R, const Blk &b, int c[3])
 {
-    unsigned bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-    if (XCD) xcd_block(bx, by, bz);
-    int t = bx * blockDim.x + threadIdx.x;
+    int t = b.x * blockDim.x + threadIdx.x;
     if (t >= R.cnt[0] * R.cnt[1]) return false;
     int y = t / R.cnt[0];
     c[0] = R.lo[0] + (t - y * R.cnt[0]);
     c[1] = R.lo[1] + y;
-    c[2] = R.lo[2] + (int)by;
+    c[2] = R.lo[2] + (int)b.y;
     return true;
 }
 

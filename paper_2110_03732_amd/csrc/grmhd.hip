@@ -15,9 +15,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <new>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/grmhd.h"
@@ -44,6 +47,7 @@ struct TRec {
 std::mutex g_tmu;
 unsigned g_tmask = 0;
 std::vector<TRec> g_trecs;
+thread_local bool g_capturing = false;  // no event records inside a captured graph
 
 struct TScope {
     int cls;
@@ -52,7 +56,7 @@ struct TScope {
     hipEvent_t a = nullptr;
     TScope(int c, hipStream_t st, double b) : cls(c), s(st), bytes(b)
     {
-        if (g_tmask & (1u << c)) {
+        if ((g_tmask & (1u << c)) && !g_capturing) {
             if (hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
             else a = nullptr;
         }
@@ -279,85 +283,109 @@ gr_status check_state(const gr_grid *g, const gr_state *st)
 }
 
 // ---------------------------------------------------------------------------
-gr_status ghost_fill(const gr_grid *g, const Geo &G, double *cells, double *faces, hipStream_t s)
+// Kernel variants: the template instance of each tiled kernel a run uses.
+// The x/y phase tile and the z-phase tile of the cell pass are the tunables
+// (the batch autotuner picks them per class of runs).
+enum XyTile { XY_32x8 = 0, XY_64x4, XY_16x16, XY_256x1, XY_128x1, XY_64x1, XY_COUNT };
+enum CzTile { CZ_16x16 = 0, CZ_32x8, CZ_COUNT };
+const int kXyTX[XY_COUNT] = {32, 64, 16, 256, 128, 64}, kXyTY[XY_COUNT] = {8, 4, 16, 1, 1, 1};
+const int kCzTX[CZ_COUNT] = {16, 32}, kCzTZ[CZ_COUNT] = {16, 8};
+const char *kXyName[XY_COUNT] = {"32x8", "64x4", "16x16", "256x1", "128x1", "64x1"};
+const char *kCzName[CZ_COUNT] = {"16x16", "32x8"};
+
+struct Variant {
+    int rec, met, xy, cz;
+};
+// tiles a run may use: two-dimensional x/y tiles when y is active, one-row
+// tiles otherwise (the metric 1-D case only the 256-wide one)
+bool xy_allowed(const gr_grid *g, int t)
 {
-    BcArgs B;
-    bool any = false;
-    for (int d = 0; d < 3; d++)
-        for (int e = 0; e < 2; e++) {
-            B.bc[d][e] = g->bc[d][e];
-            if (G.act[d] && g->bc[d][e] != GR_FIXED) any = true;
-        }
-    if (!any) return GR_OK;
-    Region R = region(G, 0, 7);
-    long shell = rtotal(R) - (long)G.n[0] * G.n[1] * G.n[2];
-    TScope ts(KC_GHOST, s, 8.0 * shell * 11 * 2);
-    dim3 gr, bl;
-    launch_dims(R, gr, bl);
-    hipLaunchKernelGGL(k_ghost_all, gr, bl, 0, s, G, B, R, ptrs<8>(cells, G.fs), ptrs<3>(faces, G.fs));
-    LAUNCHCHK();
-    return GR_OK;
+    if (g->ndim >= 2) return t <= XY_16x16;
+    if (g->metric) return t == XY_256x1;
+    return t >= XY_256x1;
+}
+Variant default_variant(const gr_grid *g)
+{
+    Variant V;
+    V.rec = g->recon;
+    V.met = g->metric ? 1 : 0;
+    V.xy = g->ndim >= 2 ? XY_32x8 : XY_256x1;
+    V.cz = CZ_16x16;
+    return V;
 }
 
-// x (and y) phases of the explicit operator; 1-D grids take a one-row tile
-template <int REC, int MET>
-gr_status launch_xy(const Geo &G, const Phys &P, const double *sp, const double *sf, const double *met, double *Lxy,
-                    hipStream_t s)
+template <int V>
+using IC = std::integral_constant<int, V>;
+template <class F>
+void with_rm(int rec, int met, F &&f)
 {
-    // reads: 8 stage fields, 3 face fields and the metric per cell; writes 8
-    TScope ts(KC_SWEEP, s, 8.0 * G.n[0] * G.n[1] * G.n[2] * (8 + 3 + 2 * MET + 8));
-    if (G.act[1]) {
-        constexpr int TX = 32, TY = 8;
-        dim3 grid((G.n[0] + TX - 1) / TX, (G.n[1] + TY - 1) / TY, G.n[2]);
-        hipLaunchKernelGGL((k_xy<REC, MET, TX, TY>), grid, dim3(TX * TY), 0, s, G, P, cptrs<8>(sp, G.fs),
-                           cptrs<3>(sf, G.fs), cptrs<2>(met, G.fs), ptrs<8>(Lxy, G.fs));
-    } else {
-        constexpr int TX = 256, TY = 1;
-        dim3 grid((G.n[0] + TX - 1) / TX, G.n[1], G.n[2]);
-        hipLaunchKernelGGL((k_xy<REC, MET, TX, TY>), grid, dim3(TX * TY), 0, s, G, P, cptrs<8>(sp, G.fs),
-                           cptrs<3>(sf, G.fs), cptrs<2>(met, G.fs), ptrs<8>(Lxy, G.fs));
+    auto m = [&](auto R) {
+        if (met) f(R, IC<1>{});
+        else f(R, IC<0>{});
+    };
+    if (rec == GR_MINMOD) m(IC<GR_MINMOD>{});
+    else if (rec == GR_MC) m(IC<GR_MC>{});
+    else m(IC<GR_PPM>{});
+}
+template <class F>
+void with_xy(int t, F &&f)
+{
+    switch (t) {
+    case XY_32x8: f(IC<32>{}, IC<8>{}); break;
+    case XY_64x4: f(IC<64>{}, IC<4>{}); break;
+    case XY_16x16: f(IC<16>{}, IC<16>{}); break;
+    case XY_256x1: f(IC<256>{}, IC<1>{}); break;
+    case XY_128x1: f(IC<128>{}, IC<1>{}); break;
+    default: f(IC<64>{}, IC<1>{}); break;
     }
-    LAUNCHCHK();
-    return GR_OK;
 }
-
-// edge EMFs of direction K on the edges of the interior plus one layer in a and b
-template <int REC, int MET, int K>
-gr_status launch_ct(const Geo &G, const double *met, const double *sp, const double *sf, double *EM, hipStream_t s)
+template <class F>
+void with_cz(int t, F &&f)
 {
-    constexpr int a = (K + 1) % 3, b = (K + 2) % 3;
-    if (!G.act[a] && !G.act[b]) return GR_OK;
-    Region Re = region(G, (1 << a) | (1 << b));
-    const int *T = CtTile<K>::T;
-    dim3 grid((Re.cnt[0] + T[0] - 1) / T[0], (Re.cnt[1] + T[1] - 1) / T[1], (Re.cnt[2] + T[2] - 1) / T[2]);
-    // reads E_k, q_B^a, q_B^b and the metric per edge point; writes one EMF
-    TScope ts(KC_CT, s, 8.0 * rtotal(Re) * (3 + 2 * MET + 1));
-    hipLaunchKernelGGL((k_ct<REC, MET, K>), grid, dim3(kBlock), 0, s, G, Re, sp + (5 + K) * G.fs, cptrs<3>(sf, G.fs),
-                       cptrs<2>(met, G.fs), EM + (size_t)K * G.fs);
-    LAUNCHCHK();
-    return GR_OK;
+    if (t == CZ_32x8) f(IC<32>{}, IC<8>{});
+    else f(IC<16>{}, IC<16>{});
 }
-
-template <int REC, int MET>
-gr_status launch_L(const Geo &G, const Phys &P, const double *met, const double *sp, const double *sf, double *Lxy,
-                   double *EM, hipStream_t s)
+// instances that no allowed variant selects are not compiled
+template <int MET, int TX, int TY>
+constexpr bool xy_compiled()
 {
-    gr_status r;
-    if ((r = launch_xy<REC, MET>(G, P, sp, sf, met, Lxy, s)) != GR_OK) return r;
-    if ((r = launch_ct<REC, MET, 2>(G, met, sp, sf, EM, s)) != GR_OK) return r;
-    if ((r = launch_ct<REC, MET, 0>(G, met, sp, sf, EM, s)) != GR_OK) return r;
-    if ((r = launch_ct<REC, MET, 1>(G, met, sp, sf, EM, s)) != GR_OK) return r;
-    return GR_OK;
+    return !(MET == 1 && TY == 1 && TX != 256);
 }
 
-template <int REC, int MET>
-gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t s)
+const int kCtOrder[3] = {2, 0, 1};
+
+// Everything one pass of one run launches, in launch order: ghost fill,
+// x/y phases, the three EMF components, the face update, the cell pass.
+struct PassPlan {
+    bool ghost = false, xy = false, face = false, swz = false;
+    bool ct[3] = {false, false, false};
+    GhostArgs gh;
+    XyArgs xya;
+    CtArgs cta[3];
+    FaceArgs fa;
+    CellArgs ca;
+    double gh_bytes = 0, xy_bytes = 0, ct_bytes[3] = {0, 0, 0}, fa_bytes = 0, ca_bytes = 0;
+};
+
+GridDims flat_dims(const Region &R)
+{
+    long plane = (long)R.cnt[0] * R.cnt[1];
+    GridDims d;
+    d.x = (unsigned)((plane + kBlock - 1) / kBlock);
+    d.y = (unsigned)R.cnt[2];
+    d.z = 1;
+    return d;
+}
+unsigned nblk(const GridDims &d) { return d.x * d.y * d.z; }
+
+gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Variant &V, PassPlan &pl)
 {
     Geo G = make_geo(g);
     Phys P = make_phys(g);
     Tableau T = tableau(g->imex);
     Layout Ly = layout(g);
     if (p < 0 || p > T.s) return GR_EINVAL;
+    const int MET = V.met;
     const bool fin = (p == T.s);
     const bool withL = (p >= 1) && needL(T, p - 1);
     StageArgs A;
@@ -381,11 +409,60 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
     double *sf_prev = (p >= 1) ? stage_face(p - 1) : nullptr;
     double *Lxy = wfield(st, G, Ly.Lxy), *EM = wfield(st, G, Ly.EM);
     const double *met = st->metric;
+    const double ncell = (double)G.n[0] * G.n[1] * G.n[2];
+
     if (withL) {
-        gr_status r = ghost_fill(g, G, sp_prev, sf_prev, s);
-        if (r != GR_OK) return r;
-        r = launch_L<REC, MET>(G, P, met, sp_prev, sf_prev, Lxy, EM, s);
-        if (r != GR_OK) return r;
+        // ghost points of the stage p-1 block
+        BcArgs B;
+        bool any = false;
+        for (int d = 0; d < 3; d++)
+            for (int e = 0; e < 2; e++) {
+                B.bc[d][e] = g->bc[d][e];
+                if (G.act[d] && g->bc[d][e] != GR_FIXED) any = true;
+            }
+        if (any) {
+            pl.ghost = true;
+            GhostArgs &a = pl.gh;
+            a.G = G;
+            a.B = B;
+            a.R = region(G, 0, 7);
+            a.cells = ptrs<8>(sp_prev, G.fs);
+            a.faces = ptrs<3>(sf_prev, G.fs);
+            a.gd = flat_dims(a.R);
+            pl.gh_bytes = 8.0 * (rtotal(a.R) - ncell) * 11 * 2;
+        }
+        // x/y phases: reads 8 stage fields, 3 face fields, the metric; writes 8
+        pl.xy = true;
+        XyArgs &x = pl.xya;
+        x.G = G;
+        x.P = P;
+        x.sp = cptrs<8>(sp_prev, G.fs);
+        x.sf = cptrs<3>(sf_prev, G.fs);
+        x.met = cptrs<2>(met, G.fs);
+        x.Lxy = ptrs<8>(Lxy, G.fs);
+        const int TX = kXyTX[V.xy], TY = kXyTY[V.xy];
+        x.gd.x = (G.n[0] + TX - 1) / TX;
+        x.gd.y = (G.n[1] + TY - 1) / TY;
+        x.gd.z = G.n[2];
+        pl.xy_bytes = 8.0 * ncell * (8 + 3 + 2 * MET + 8);
+        // EMFs: reads E_k, two face fields and the metric per edge; writes one
+        for (int i = 0; i < 3; i++) {
+            const int K = kCtOrder[i], a = (K + 1) % 3, b = (K + 2) % 3;
+            if (!G.act[a] && !G.act[b]) continue;
+            pl.ct[i] = true;
+            CtArgs &c = pl.cta[i];
+            c.G = G;
+            c.R = region(G, (1 << a) | (1 << b));
+            c.Ek = sp_prev + (size_t)(5 + K) * G.fs;
+            c.sf = cptrs<3>(sf_prev, G.fs);
+            c.met = cptrs<2>(met, G.fs);
+            c.EM = EM + (size_t)K * G.fs;
+            const int *Tt = K == 2 ? CtTile<2>::T : (K == 0 ? CtTile<0>::T : CtTile<1>::T);
+            c.gd.x = (c.R.cnt[0] + Tt[0] - 1) / Tt[0];
+            c.gd.y = (c.R.cnt[1] + Tt[1] - 1) / Tt[1];
+            c.gd.z = (c.R.cnt[2] + Tt[2] - 1) / Tt[2];
+            pl.ct_bytes[i] = 8.0 * rtotal(c.R) * (3 + 2 * MET + 1);
+        }
     }
     // faces of this pass
     double *fout = fin ? st->face : stage_face(p);
@@ -395,25 +472,31 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
         if (A.cR[j] != 0.0) nRst++;
     }
     if (fin || !faces_are_n(T, p)) {
-        Region R = region(G, 7);
-        FaceLs Ls;
-        std::memset(&Ls, 0, sizeof(Ls));
+        pl.face = true;
+        FaceArgs &f = pl.fa;
+        f.G = G;
+        f.R = region(G, 7);
+        f.A = A;
+        f.EM = cptrs<3>(EM, G.fs);
+        f.fn = cptrs<3>(st->face, G.fs);
+        std::memset(&f.Ls, 0, sizeof(f.Ls));
         for (int d = 0; d < 3; d++) {
             for (int j = 0; j < 4; j++)
-                Ls.Lf[j][d] = (j < T.s) ? wfield(st, G, Ly.L + 11 * (size_t)j + 8 + d) : nullptr;
-            Ls.Lst[d] = withL ? wfield(st, G, Ly.L + 11 * (size_t)(p - 1) + 8 + d) : nullptr;
+                f.Ls.Lf[j][d] = (j < T.s) ? wfield(st, G, Ly.L + 11 * (size_t)j + 8 + d) : nullptr;
+            f.Ls.Lst[d] = withL ? wfield(st, G, Ly.L + 11 * (size_t)(p - 1) + 8 + d) : nullptr;
         }
+        f.fout = ptrs<3>(fout, G.fs);
+        f.gd = flat_dims(f.R);
         double nf = 0.0;
         for (int d = 0; d < 3; d++) nf += (double)rtotal(region(G, 1 << d));
-        TScope ts(KC_FACE_UPDATE, s, 8.0 * (nf * (1 + nLst + 1 + (int)withL) + (withL ? 3.0 * rtotal(R) : 0.0)));
-        dim3 gr, bl;
-        launch_dims(R, gr, bl);
-        hipLaunchKernelGGL(k_face_update, gr, bl, 0, s, G, R, A, cptrs<3>(EM, G.fs), cptrs<3>(st->face, G.fs), Ls,
-                           ptrs<3>(fout, G.fs));
-        LAUNCHCHK();
+        pl.fa_bytes = 8.0 * (nf * (1 + nLst + 1 + (int)withL) + (withL ? 3.0 * rtotal(f.R) : 0.0));
     }
     // cells
-    CellIO io;
+    CellArgs &c = pl.ca;
+    c.G = G;
+    c.P = P;
+    c.A = A;
+    CellIO &io = c.io;
     std::memset(&io, 0, sizeof(io));
     for (int v = 0; v < 8; v++) io.Lxy[v] = Lxy + (size_t)v * G.fs;
     for (int v = 0; v < 8; v++) io.spm[v] = sp_prev ? sp_prev + v * G.fs : nullptr;
@@ -435,33 +518,516 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
     io.met[0] = met;
     io.met[1] = met ? met + G.fs : nullptr;
     io.nfail = wcounter(st);
-    Region Rc = region(G, 0);
+    c.R = region(G, 0);
+    pl.swz = withL && G.act[2];
+    if (pl.swz) {
+        const int TX = kCzTX[V.cz], TZ = kCzTZ[V.cz];
+        c.gd.x = (c.R.cnt[0] + TX - 1) / TX;
+        c.gd.y = c.R.cnt[1];
+        c.gd.z = (c.R.cnt[2] + TZ - 1) / TZ;
+    } else {
+        c.gd = flat_dims(c.R);
+    }
     double cb = 8 + 3 + 2 * MET + 8 * nLst + 3 * nRst + (fin ? 1 : 3);  // q, faces, metric, L, R, guess
     if (withL) cb += 8 + 8 + 3;                                          // Lxy, stage p-1 prims/E, faces
     cb += fin ? (8 + 5) : (8 + 3);                                       // outputs
     if (withL) cb += 8;                                                  // stored L
-    TScope ts(KC_CELL_UPDATE, s, 8.0 * rtotal(Rc) * cb);
-    if (withL && G.act[2]) {
-        constexpr int TX = 16, TZ = 16;
-        dim3 grid((Rc.cnt[0] + TX - 1) / TX, Rc.cnt[1], (Rc.cnt[2] + TZ - 1) / TZ);
-        hipLaunchKernelGGL((k_cell_update<REC, MET, 1, TX, TZ>), grid, dim3(kBlock), 0, s, G, P, Rc, A, io);
-    } else {
-        dim3 gr, bl;
-        launch_dims(Rc, gr, bl);
-        hipLaunchKernelGGL((k_cell_update<REC, MET, 0, 1, 1>), gr, bl, 0, s, G, P, Rc, A, io);
+    pl.ca_bytes = 8.0 * ncell * cb;
+    return GR_OK;
+}
+
+dim3 d3(const GridDims &g) { return dim3(g.x, g.y, g.z); }
+
+// ---- plain launches (one run, hardware block ids)
+void launch_xy(const Variant &V, const XyArgs &a, hipStream_t s)
+{
+    with_rm(V.rec, V.met, [&](auto R, auto M) {
+        with_xy(V.xy, [&](auto TX, auto TY) {
+            if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value>())
+                hipLaunchKernelGGL((k_xy<decltype(R)::value, decltype(M)::value, decltype(TX)::value,
+                                         decltype(TY)::value>),
+                                   d3(a.gd), dim3(decltype(TX)::value * decltype(TY)::value), 0, s, a);
+        });
+    });
+}
+void launch_ct(const Variant &V, int K, const CtArgs &a, hipStream_t s)
+{
+    with_rm(V.rec, V.met, [&](auto R, auto M) {
+        constexpr int r = decltype(R)::value, m = decltype(M)::value;
+        if (K == 2) hipLaunchKernelGGL((k_ct<r, m, 2>), d3(a.gd), dim3(kBlock), 0, s, a);
+        else if (K == 0) hipLaunchKernelGGL((k_ct<r, m, 0>), d3(a.gd), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_ct<r, m, 1>), d3(a.gd), dim3(kBlock), 0, s, a);
+    });
+}
+void launch_cell(const Variant &V, bool swz, const CellArgs &a, hipStream_t s)
+{
+    with_rm(V.rec, V.met, [&](auto R, auto M) {
+        constexpr int r = decltype(R)::value, m = decltype(M)::value;
+        if (!swz) {
+            hipLaunchKernelGGL((k_cell_update<r, m, 0, 1, 1>), d3(a.gd), dim3(kBlock), 0, s, a);
+            return;
+        }
+        with_cz(V.cz, [&](auto TX, auto TZ) {
+            hipLaunchKernelGGL((k_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value>), d3(a.gd),
+                               dim3(kBlock), 0, s, a);
+        });
+    });
+}
+
+gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
+{
+    if (pl.ghost) {
+        TScope ts(KC_GHOST, s, pl.gh_bytes);
+        hipLaunchKernelGGL(k_ghost_all, d3(pl.gh.gd), dim3(kBlock), 0, s, pl.gh);
+        LAUNCHCHK();
+    }
+    if (pl.xy) {
+        TScope ts(KC_SWEEP, s, pl.xy_bytes);
+        launch_xy(V, pl.xya, s);
+        LAUNCHCHK();
+    }
+    for (int i = 0; i < 3; i++) {
+        if (!pl.ct[i]) continue;
+        TScope ts(KC_CT, s, pl.ct_bytes[i]);
+        launch_ct(V, kCtOrder[i], pl.cta[i], s);
+        LAUNCHCHK();
+    }
+    if (pl.face) {
+        TScope ts(KC_FACE_UPDATE, s, pl.fa_bytes);
+        hipLaunchKernelGGL(k_face_update, d3(pl.fa.gd), dim3(kBlock), 0, s, pl.fa);
+        LAUNCHCHK();
+    }
+    {
+        TScope ts(KC_CELL_UPDATE, s, pl.ca_bytes);
+        launch_cell(V, pl.swz, pl.ca, s);
+        LAUNCHCHK();
+    }
+    return GR_OK;
+}
+
+gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t s)
+{
+    Variant V = default_variant(g);
+    PassPlan pl;
+    gr_status r = plan_pass(g, st, p, dt, V, pl);
+    if (r != GR_OK) return r;
+    return launch_plan(V, pl, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent runs.  One step of every run is a fixed list of
+// batched launches: for each pass and each kernel class, the runs sharing a
+// template instance go into one launch whose 1-D grid concatenates their block
+// ranges (a prefix array maps a block to its run and to its position in that
+// run's own grid; the per-run kernel arguments sit in a device array).  The
+// list is captured once into a HIP graph and replayed per step.
+struct BLaunch {
+    int cls = 0;
+    int K = 0;
+    Variant V{};
+    bool swz = false;
+    size_t args_off = 0, start_off = 0;  // offsets into the batch's device block
+    const void *args = nullptr;
+    const unsigned *start = nullptr;
+    int n = 0;
+    unsigned total = 0;
+    double bytes = 0.0;
+};
+
+}  // namespace
+
+struct gr_batch {
+    std::vector<gr_grid> grids;
+    std::vector<gr_state> states;
+    std::vector<double> dt;
+    std::vector<Variant> var;
+    int s = 0;
+    std::vector<BLaunch> launches;
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
+    double bytes_step = 0.0;
+    long cells = 0;
+};
+
+namespace {
+
+// host staging of the device block: 256-byte aligned pieces
+struct Staging {
+    std::vector<char> buf;
+    size_t put(const void *p, size_t n)
+    {
+        size_t o = (buf.size() + 255) / 256 * 256;
+        buf.resize(o + n);
+        std::memcpy(buf.data() + o, p, n);
+        return o;
+    }
+};
+
+template <class A>
+void add_group(Staging &stg, std::vector<BLaunch> &out, BLaunch proto, const std::vector<const A *> &args,
+               const std::vector<double> &bytes)
+{
+    if (args.empty()) return;
+    std::vector<A> arr;
+    std::vector<unsigned> start(1, 0u);
+    double by = 0.0;
+    for (size_t i = 0; i < args.size(); i++) {
+        arr.push_back(*args[i]);
+        start.push_back(start.back() + nblk(args[i]->gd));
+        by += bytes[i];
+    }
+    proto.n = (int)args.size();
+    proto.total = start.back();
+    proto.bytes = by;
+    proto.args_off = stg.put(arr.data(), arr.size() * sizeof(A));
+    proto.start_off = stg.put(start.data(), start.size() * sizeof(unsigned));
+    if (proto.total > 0) out.push_back(proto);
+}
+
+// build the launch list of one step (or of one pass p, or only some classes
+// when tuning) for the runs selected by `use`
+gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::vector<char> &use, Staging &stg,
+                         std::vector<BLaunch> &out)
+{
+    const int nr = (int)b->grids.size();
+    for (int p = 0; p <= b->s; p++) {
+        if (p_only >= 0 && p != p_only) continue;
+        std::vector<PassPlan> pl(nr);
+        for (int r = 0; r < nr; r++) {
+            if (!use[r]) continue;
+            gr_status e = plan_pass(&b->grids[r], &b->states[r], p, b->dt[r], b->var[r], pl[r]);
+            if (e != GR_OK) return e;
+        }
+        // ghost fill
+        if (cls_mask & (1u << KC_GHOST)) {
+            std::vector<const GhostArgs *> a;
+            std::vector<double> by;
+            for (int r = 0; r < nr; r++)
+                if (use[r] && pl[r].ghost) {
+                    a.push_back(&pl[r].gh);
+                    by.push_back(pl[r].gh_bytes);
+                }
+            BLaunch L;
+            L.cls = KC_GHOST;
+            add_group(stg, out, L, a, by);
+        }
+        // x/y phases, grouped by (recon, metric, tile)
+        if (cls_mask & (1u << KC_SWEEP)) {
+            for (int rec = 0; rec < 3; rec++)
+                for (int met = 0; met < 2; met++)
+                    for (int t = 0; t < XY_COUNT; t++) {
+                        std::vector<const XyArgs *> a;
+                        std::vector<double> by;
+                        for (int r = 0; r < nr; r++) {
+                            const Variant &V = b->var[r];
+                            if (use[r] && pl[r].xy && V.rec == rec && V.met == met && V.xy == t) {
+                                a.push_back(&pl[r].xya);
+                                by.push_back(pl[r].xy_bytes);
+                            }
+                        }
+                        BLaunch L;
+                        L.cls = KC_SWEEP;
+                        L.V = Variant{rec, met, t, 0};
+                        add_group(stg, out, L, a, by);
+                    }
+        }
+        // EMFs, grouped by (component, recon, metric)
+        if (cls_mask & (1u << KC_CT)) {
+            for (int i = 0; i < 3; i++)
+                for (int rec = 0; rec < 3; rec++)
+                    for (int met = 0; met < 2; met++) {
+                        std::vector<const CtArgs *> a;
+                        std::vector<double> by;
+                        for (int r = 0; r < nr; r++) {
+                            const Variant &V = b->var[r];
+                            if (use[r] && pl[r].ct[i] && V.rec == rec && V.met == met) {
+                                a.push_back(&pl[r].cta[i]);
+                                by.push_back(pl[r].ct_bytes[i]);
+                            }
+                        }
+                        BLaunch L;
+                        L.cls = KC_CT;
+                        L.K = kCtOrder[i];
+                        L.V = Variant{rec, met, 0, 0};
+                        add_group(stg, out, L, a, by);
+                    }
+        }
+        // face update
+        if (cls_mask & (1u << KC_FACE_UPDATE)) {
+            std::vector<const FaceArgs *> a;
+            std::vector<double> by;
+            for (int r = 0; r < nr; r++)
+                if (use[r] && pl[r].face) {
+                    a.push_back(&pl[r].fa);
+                    by.push_back(pl[r].fa_bytes);
+                }
+            BLaunch L;
+            L.cls = KC_FACE_UPDATE;
+            add_group(stg, out, L, a, by);
+        }
+        // cell pass, grouped by (recon, metric, z phase, tile)
+        if (cls_mask & (1u << KC_CELL_UPDATE)) {
+            for (int rec = 0; rec < 3; rec++)
+                for (int met = 0; met < 2; met++)
+                    for (int sw = 0; sw < 2; sw++)
+                        for (int t = 0; t < (sw ? CZ_COUNT : 1); t++) {
+                            std::vector<const CellArgs *> a;
+                            std::vector<double> by;
+                            for (int r = 0; r < nr; r++) {
+                                const Variant &V = b->var[r];
+                                if (use[r] && V.rec == rec && V.met == met && (int)pl[r].swz == sw &&
+                                    (!sw || V.cz == t)) {
+                                    a.push_back(&pl[r].ca);
+                                    by.push_back(pl[r].ca_bytes);
+                                }
+                            }
+                            BLaunch L;
+                            L.cls = KC_CELL_UPDATE;
+                            L.V = Variant{rec, met, 0, t};
+                            L.swz = sw;
+                            add_group(stg, out, L, a, by);
+                        }
+        }
+    }
+    return GR_OK;
+}
+
+gr_status upload(Staging &stg, std::vector<BLaunch> &ls, void **dev, size_t *bytes, hipStream_t s)
+{
+    *dev = nullptr;
+    *bytes = stg.buf.size();
+    if (stg.buf.empty()) return GR_OK;
+    HIPCHK(hipMalloc(dev, stg.buf.size()));
+    if (hipMemcpyAsync(*dev, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipFree(*dev);
+        *dev = nullptr;
+        return GR_EHIP;
+    }
+    for (auto &L : ls) {
+        L.args = (const char *)*dev + L.args_off;
+        L.start = (const unsigned *)((const char *)*dev + L.start_off);
+    }
+    return GR_OK;
+}
+
+gr_status launch_b(const BLaunch &L, hipStream_t s)
+{
+    if (L.total == 0) return GR_OK;
+    const dim3 grid(L.total);
+    switch (L.cls) {
+    case KC_GHOST:
+        hipLaunchKernelGGL(kb_ghost_all, grid, dim3(kBlock), 0, s, (const GhostArgs *)L.args, L.start, L.n);
+        break;
+    case KC_SWEEP:
+        with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
+            with_xy(L.V.xy, [&](auto TX, auto TY) {
+                if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value>())
+                    hipLaunchKernelGGL((kb_xy<decltype(R)::value, decltype(M)::value, decltype(TX)::value,
+                                              decltype(TY)::value>),
+                                       grid, dim3(decltype(TX)::value * decltype(TY)::value), 0, s,
+                                       (const XyArgs *)L.args, L.start, L.n);
+            });
+        });
+        break;
+    case KC_CT:
+        with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
+            constexpr int r = decltype(R)::value, m = decltype(M)::value;
+            const CtArgs *a = (const CtArgs *)L.args;
+            if (L.K == 2) hipLaunchKernelGGL((kb_ct<r, m, 2>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+            else if (L.K == 0) hipLaunchKernelGGL((kb_ct<r, m, 0>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+            else hipLaunchKernelGGL((kb_ct<r, m, 1>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+        });
+        break;
+    case KC_FACE_UPDATE:
+        hipLaunchKernelGGL(kb_face_update, grid, dim3(kBlock), 0, s, (const FaceArgs *)L.args, L.start, L.n);
+        break;
+    default:
+        with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
+            constexpr int r = decltype(R)::value, m = decltype(M)::value;
+            const CellArgs *a = (const CellArgs *)L.args;
+            if (!L.swz) {
+                hipLaunchKernelGGL((kb_cell_update<r, m, 0, 1, 1>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+                return;
+            }
+            with_cz(L.V.cz, [&](auto TX, auto TZ) {
+                hipLaunchKernelGGL((kb_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value>), grid,
+                                   dim3(kBlock), 0, s, a, L.start, L.n);
+            });
+        });
+        break;
     }
     LAUNCHCHK();
     return GR_OK;
 }
 
-template <int MET>
-gr_status dispatch_rec(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t s)
+gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s)
 {
-    switch (g->recon) {
-    case GR_MINMOD: return run_pass<GR_MINMOD, MET>(g, st, p, dt, s);
-    case GR_MC: return run_pass<GR_MC, MET>(g, st, p, dt, s);
-    default: return run_pass<GR_PPM, MET>(g, st, p, dt, s);
+    for (const auto &L : ls) {
+        TScope ts(L.cls, s, L.bytes);
+        gr_status e = launch_b(L, s);
+        if (e != GR_OK) return e;
     }
+    return GR_OK;
+}
+
+void drop_graph(gr_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+gr_status rebuild(gr_batch *b, hipStream_t s)
+{
+    drop_graph(b);
+    if (b->dev) (void)hipFree(b->dev);
+    b->dev = nullptr;
+    b->launches.clear();
+    Staging stg;
+    std::vector<char> all(b->grids.size(), 1);
+    gr_status e = build_launches(b, -1, ~0u, all, stg, b->launches);
+    if (e != GR_OK) return e;
+    e = upload(stg, b->launches, &b->dev, &b->dev_bytes, s);
+    if (e != GR_OK) return e;
+    b->bytes_step = 0.0;
+    for (const auto &L : b->launches) b->bytes_step += L.bytes;
+    return GR_OK;
+}
+
+// ---- autotuner.  Runs are classed by (recon, metric, dimensionality); for
+// each class the x/y tile (and for 3-D runs the z-phase tile of the cell
+// pass) is timed over the batch's own runs of that class and the fastest kept.
+// A cache file holds one line per decision: "xy|cz rec met ndim tile".
+struct TuneKey {
+    int what, rec, met, ndim;
+    bool operator==(const TuneKey &o) const
+    {
+        return what == o.what && rec == o.rec && met == o.met && ndim == o.ndim;
+    }
+};
+
+double time_list(const std::vector<BLaunch> &ls, hipStream_t s, int reps)
+{
+    hipEvent_t a, e;
+    if (hipEventCreate(&a) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return -1.0;
+    }
+    double ms = -1.0;
+    if (launch_list(ls, s) == GR_OK && hipEventRecord(a, s) == hipSuccess) {
+        bool ok = true;
+        for (int i = 0; i < reps && ok; i++) ok = launch_list(ls, s) == GR_OK;
+        float f = 0.0f;
+        if (ok && hipEventRecord(e, s) == hipSuccess && hipEventSynchronize(e) == hipSuccess &&
+            hipEventElapsedTime(&f, a, e) == hipSuccess)
+            ms = f / reps;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(e);
+    return ms;
+}
+
+gr_status tune(gr_batch *b, const char *cache, hipStream_t s)
+{
+    const int nr = (int)b->grids.size();
+    std::vector<std::pair<TuneKey, int>> known;
+    if (cache && cache[0]) {
+        if (FILE *f = std::fopen(cache, "r")) {
+            char w[8], t[16];
+            int rec, met, nd;
+            while (std::fscanf(f, "%7s %d %d %d %15s", w, &rec, &met, &nd, t) == 5) {
+                TuneKey k{w[0] == 'x' ? 0 : 1, rec, met, nd};
+                int tile = -1;
+                for (int i = 0; i < (k.what == 0 ? XY_COUNT : CZ_COUNT); i++)
+                    if (!std::strcmp(t, k.what == 0 ? kXyName[i] : kCzName[i])) tile = i;
+                if (tile >= 0) known.push_back({k, tile});
+            }
+            std::fclose(f);
+        }
+    }
+    // the first pass that evaluates the explicit operator
+    Tableau T = tableau(b->grids[0].imex);
+    int pL = 1;
+    while (pL <= T.s && !needL(T, pL - 1)) pL++;
+    // the failure counters are restored after the timing launches
+    std::vector<unsigned long long> cnt(nr);
+    for (int r = 0; r < nr; r++)
+        HIPCHK(hipMemcpyAsync(&cnt[r], wcounter(&b->states[r]), sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<std::pair<TuneKey, int>> fresh;
+    gr_status status = GR_OK;
+    for (int what = 0; what < 2 && status == GR_OK; what++) {
+        std::vector<TuneKey> keys;
+        for (int r = 0; r < nr; r++) {
+            const gr_grid &g = b->grids[r];
+            if (what == 1 && g.ndim < 3) continue;
+            TuneKey k{what, (int)g.recon, g.metric ? 1 : 0, g.ndim};
+            bool seen = false;
+            for (auto &q : keys) seen |= q == k;
+            if (!seen) keys.push_back(k);
+        }
+        for (const TuneKey &k : keys) {
+            std::vector<char> use(nr, 0);
+            for (int r = 0; r < nr; r++) {
+                const gr_grid &g = b->grids[r];
+                use[r] = ((int)g.recon == k.rec && (g.metric ? 1 : 0) == k.met && g.ndim == k.ndim);
+            }
+            int best = -1;
+            for (auto &q : known)
+                if (q.first == k) best = q.second;
+            if (best < 0) {
+                double bms = 1e300;
+                const int nc = what == 0 ? XY_COUNT : CZ_COUNT;
+                for (int t = 0; t < nc && status == GR_OK; t++) {
+                    int r0 = 0;
+                    while (!use[r0]) r0++;
+                    if (what == 0 && !xy_allowed(&b->grids[r0], t)) continue;
+                    for (int r = 0; r < nr; r++)
+                        if (use[r]) (what == 0 ? b->var[r].xy : b->var[r].cz) = t;
+                    Staging stg;
+                    std::vector<BLaunch> ls;
+                    status = build_launches(b, pL, what == 0 ? (1u << KC_SWEEP) : (1u << KC_CELL_UPDATE), use, stg,
+                                            ls);
+                    if (status != GR_OK) break;
+                    void *dev = nullptr;
+                    size_t nb = 0;
+                    status = upload(stg, ls, &dev, &nb, s);
+                    if (status != GR_OK) break;
+                    double ms = time_list(ls, s, 5);
+                    (void)hipFree(dev);
+                    if (ms < 0.0) {
+                        status = GR_EHIP;
+                        break;
+                    }
+                    if (ms < bms) {
+                        bms = ms;
+                        best = t;
+                    }
+                }
+                if (best >= 0) fresh.push_back({k, best});
+            }
+            for (int r = 0; r < nr; r++)
+                if (use[r] && best >= 0) (what == 0 ? b->var[r].xy : b->var[r].cz) = best;
+        }
+    }
+    for (int r = 0; r < nr; r++)
+        HIPCHK(hipMemcpyAsync(wcounter(&b->states[r]), &cnt[r], sizeof(unsigned long long), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (status == GR_OK && cache && cache[0] && !fresh.empty()) {
+        if (FILE *f = std::fopen(cache, "a")) {
+            for (auto &q : fresh)
+                std::fprintf(f, "%s %d %d %d %s\n", q.first.what == 0 ? "xy" : "cz", q.first.rec, q.first.met,
+                             q.first.ndim, q.first.what == 0 ? kXyName[q.second] : kCzName[q.second]);
+            std::fclose(f);
+        }
+    }
+    return status;
 }
 
 }  // namespace
@@ -629,7 +1195,7 @@ gr_status gr_imex_stage(const gr_grid *g, gr_state *st, int p, double dt, hipStr
     v = check_state(g, st);
     if (v != GR_OK) return v;
     if (!(dt > 0.0)) return GR_EINVAL;
-    return g->metric ? dispatch_rec<1>(g, st, p, dt, s) : dispatch_rec<0>(g, st, p, dt, s);
+    return run_pass(g, st, p, dt, s);
 }
 
 gr_status gr_step(const gr_grid *g, gr_state *st, double dt, hipStream_t s)
@@ -665,11 +1231,15 @@ gr_status gr_con2prim(const gr_grid *g, gr_state *st, hipStream_t s)
     io.met[0] = st->metric;
     io.met[1] = st->metric ? st->metric + G.fs : nullptr;
     io.nfail = wcounter(st);
-    Region Rc = region(G, 0);
-    dim3 gr, bl;
-    launch_dims(Rc, gr, bl);
-    if (g->metric) hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 1, 0, 1, 1>), gr, bl, 0, s, G, P, Rc, A, io);
-    else hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 0, 0, 1, 1>), gr, bl, 0, s, G, P, Rc, A, io);
+    CellArgs ca;
+    ca.G = G;
+    ca.P = P;
+    ca.R = region(G, 0);
+    ca.A = A;
+    ca.io = io;
+    ca.gd = flat_dims(ca.R);
+    if (g->metric) hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 1, 0, 1, 1>), d3(ca.gd), dim3(kBlock), 0, s, ca);
+    else hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 0, 0, 1, 1>), d3(ca.gd), dim3(kBlock), 0, s, ca);
     LAUNCHCHK();
     return GR_OK;
 }
@@ -767,6 +1337,119 @@ gr_status gr_fail_count(const gr_grid *g, const gr_state *st, unsigned long long
     if (!count) return GR_EINVAL;
     HIPCHK(hipMemcpyAsync(count, wcounter(st), sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    return GR_OK;
+}
+
+// ---------------------------------------------------------------------------
+gr_status gr_batch_create(gr_batch **out, const gr_grid *grids, const gr_state *states, const double *dt, int nruns,
+                          const char *tune_cache, hipStream_t s)
+{
+    if (!out || !grids || !states || !dt || nruns < 1) return GR_EINVAL;
+    *out = nullptr;
+    for (int r = 0; r < nruns; r++) {
+        gr_status v = gr_validate(&grids[r]);
+        if (v != GR_OK) return v;
+        v = check_state(&grids[r], &states[r]);
+        if (v != GR_OK) return v;
+        if (!(dt[r] > 0.0)) return GR_EINVAL;
+        if (grids[r].imex != grids[0].imex) return GR_EUNSUPPORTED;
+    }
+    gr_batch *b = new (std::nothrow) gr_batch;
+    if (!b) return GR_ENOMEM;
+    b->grids.assign(grids, grids + nruns);
+    b->states.assign(states, states + nruns);
+    b->dt.assign(dt, dt + nruns);
+    b->s = tableau(grids[0].imex).s;
+    b->cells = 0;
+    for (int r = 0; r < nruns; r++) {
+        b->var.push_back(default_variant(&grids[r]));
+        Geo G = make_geo(&grids[r]);
+        b->cells += (long)G.n[0] * G.n[1] * G.n[2];
+    }
+    gr_status e = GR_OK;
+    if (tune_cache) e = tune(b, tune_cache, s);
+    if (e == GR_OK) e = rebuild(b, s);
+    if (e != GR_OK) {
+        gr_batch_destroy(b);
+        return e;
+    }
+    *out = b;
+    return GR_OK;
+}
+
+gr_status gr_batch_set_dt(gr_batch *b, const double *dt, hipStream_t s)
+{
+    if (!b || !dt) return GR_EINVAL;
+    for (size_t r = 0; r < b->dt.size(); r++)
+        if (!(dt[r] > 0.0)) return GR_EINVAL;
+    HIPCHK(hipStreamSynchronize(s));  // the old argument block may still be in use
+    b->dt.assign(dt, dt + b->dt.size());
+    return rebuild(b, s);
+}
+
+gr_status gr_batch_step(gr_batch *b, hipStream_t s)
+{
+    if (!b) return GR_EINVAL;
+    return launch_list(b->launches, s);
+}
+
+gr_status gr_batch_run(gr_batch *b, int nsteps, hipStream_t s)
+{
+    if (!b || nsteps < 0) return GR_EINVAL;
+    if (!b->exec) {
+        if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        g_capturing = true;
+        hipError_t c = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        gr_status e = GR_OK;
+        if (c == hipSuccess) {
+            e = launch_list(b->launches, b->cap);
+            c = hipStreamEndCapture(b->cap, &b->graph);
+        }
+        g_capturing = false;
+        if (c != hipSuccess || e != GR_OK) {
+            drop_graph(b);
+            return GR_EHIP;
+        }
+        if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(b);
+            return GR_EHIP;
+        }
+    }
+    for (int i = 0; i < nsteps; i++) HIPCHK(hipGraphLaunch(b->exec, s));
+    return GR_OK;
+}
+
+gr_status gr_batch_stats(const gr_batch *b, int *launches_per_step, double *alg_bytes_per_step, long *cells)
+{
+    if (!b) return GR_EINVAL;
+    if (launches_per_step) *launches_per_step = (int)b->launches.size();
+    if (alg_bytes_per_step) *alg_bytes_per_step = b->bytes_step;
+    if (cells) *cells = b->cells;
+    return GR_OK;
+}
+
+gr_status gr_batch_tiles(const gr_batch *b, int run, int *xy_tile, int *cz_tile)
+{
+    if (!b || run < 0 || run >= (int)b->var.size() || !xy_tile || !cz_tile) return GR_EINVAL;
+    *xy_tile = b->var[run].xy;
+    *cz_tile = b->var[run].cz;
+    return GR_OK;
+}
+
+const char *gr_tile_name(int which, int tile)
+{
+    if (which == 0 && tile >= 0 && tile < XY_COUNT) return kXyName[tile];
+    if (which == 1 && tile >= 0 && tile < CZ_COUNT) return kCzName[tile];
+    return "";
+}
+
+gr_status gr_batch_destroy(gr_batch *b)
+{
+    if (!b) return GR_OK;
+    drop_graph(b);
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
     return GR_OK;
 }
 

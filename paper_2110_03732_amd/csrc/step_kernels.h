@@ -56,10 +56,22 @@ __device__ __forceinline__ int map_face(const Geo &G, const BcArgs &B, int d, in
     return m;
 }
 
-__global__ void __launch_bounds__(kBlock) k_ghost_all(Geo G, BcArgs B, Region R, Ptr<8> cells, Ptr<3> faces)
+struct GhostArgs {
+    Geo G;
+    BcArgs B;
+    Region R;
+    Ptr<8> cells;
+    Ptr<3> faces;
+    GridDims gd;
+};
+__device__ __forceinline__ void ghost_body(const GhostArgs &a, Blk blk)
 {
+    const Geo &G = a.G;
+    const BcArgs &B = a.B;
+    const Ptr<8> &cells = a.cells;
+    const Ptr<3> &faces = a.faces;
     int c[3];
-    if (!region_point(R, c)) return;
+    if (!region_point(a.R, blk, c)) return;
     int s[3];
     bool move = false;
 #pragma unroll
@@ -84,6 +96,14 @@ __global__ void __launch_bounds__(kBlock) k_ghost_all(Geo G, BcArgs B, Region R,
         }
         if (mv) stb(faces.p[f], o, ldb(faces.p[f], (unsigned)lin(G, sf) << 3));
     }
+}
+__global__ void __launch_bounds__(kBlock) k_ghost_all(GhostArgs a) { ghost_body(a, blk_of(hw_linear<false>(), a.gd)); }
+__global__ void __launch_bounds__(kBlock)
+    kb_ghost_all(const GhostArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
+{
+    unsigned lb;
+    const GhostArgs &a = aa[batch_locate<false>(start, n, lb)];
+    ghost_body(a, blk_of(lb, a.gd));
 }
 
 // ---------------------------------------------------------------------------
@@ -277,19 +297,28 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
 // x and y phases of the explicit operator on a TX x TY tile of one z plane:
 // Lxy = -(dF_x/dx) - (dF_y/dy) of every interior cell (the y phase only where
 // y is active)
+struct XyArgs {
+    Geo G;
+    Phys P;
+    CPtr<8> sp;
+    CPtr<3> sf;
+    CPtr<2> met;
+    Ptr<8> Lxy;
+    GridDims gd;
+};
 template <int REC, int MET, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_xy(Geo G, Phys P, CPtr<8> sp, CPtr<3> sf, CPtr<2> met, Ptr<8> Lxy)
+__device__ __forceinline__ void xy_body(const XyArgs &a, Blk blk)
 {
+    const Geo &G = a.G;
     constexpr int LX = PhaseDims<0, TX, TY, 1>::LDS, LY = PhaseDims<1, TX, TY, 1>::LDS;
     __shared__ double lds[LX > LY ? LX : LY];
-    unsigned bx, by, bz;
-    xcd_block(bx, by, bz);
+    const unsigned bx = blk.x, by = blk.y, bz = blk.z;
     const int org[3] = {G.g[0] + (int)bx * TX, G.g[1] + (int)by * TY, G.g[2] + (int)bz};
     double L[8];
-    sweep_phase<REC, MET, 0, TX, TY, 1>(G, P, sp, sf, met, org, lds, L);
+    sweep_phase<REC, MET, 0, TX, TY, 1>(G, a.P, a.sp, a.sf, a.met, org, lds, L);
     if (G.act[1]) {
         double Ly[8];
-        sweep_phase<REC, MET, 1, TX, TY, 1>(G, P, sp, sf, met, org, lds, Ly);
+        sweep_phase<REC, MET, 1, TX, TY, 1>(G, a.P, a.sp, a.sf, a.met, org, lds, Ly);
 #pragma unroll
         for (int v = 0; v < 8; v++) L[v] += Ly[v];
     }
@@ -297,7 +326,19 @@ __global__ void __launch_bounds__(TX *TY) k_xy(Geo G, Phys P, CPtr<8> sp, CPtr<3
     if (c[0] >= G.g[0] + G.n[0] || c[1] >= G.g[1] + G.n[1]) return;
     const unsigned o = (unsigned)lin(G, c) << 3;
 #pragma unroll
-    for (int v = 0; v < 8; v++) stb(Lxy.p[v], o, L[v]);
+    for (int v = 0; v < 8; v++) stb(a.Lxy.p[v], o, L[v]);
+}
+template <int REC, int MET, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_xy(XyArgs a)
+{
+    xy_body<REC, MET, TX, TY>(a, blk_of(hw_linear<true>(), a.gd));
+}
+template <int REC, int MET, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) kb_xy(const XyArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
+{
+    unsigned lb;
+    const XyArgs &a = aa[batch_locate<true>(start, n, lb)];
+    xy_body<REC, MET, TX, TY>(a, blk_of(lb, a.gd));
 }
 
 template <int MET>
@@ -341,10 +382,23 @@ struct CtTile<0> {  // x-edges: a = y, b = z
     static constexpr int T[3] = {16, 4, 4};
 };
 
+struct CtArgs {
+    Geo G;
+    Region R;
+    const double *Ek;
+    CPtr<3> sf;
+    CPtr<2> met;
+    double *EM;
+    GridDims gd;
+};
 template <int REC, int MET, int K>
-__global__ void __launch_bounds__(kBlock) k_ct(Geo G, Region R, const double *__restrict__ Ek, CPtr<3> sf, CPtr<2> met,
-                                              double *__restrict__ EM)
+__device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
 {
+    const Geo &G = args.G;
+    const Region &R = args.R;
+    const double *__restrict__ Ek = args.Ek;
+    const CPtr<3> &sf = args.sf;
+    const CPtr<2> &met = args.met;
     constexpr int A = (K + 1) % 3, B = (K + 2) % 3;
     constexpr int T0 = CtTile<K>::T[0], T1 = CtTile<K>::T[1], T2 = CtTile<K>::T[2];
     constexpr int HB = 3;
@@ -355,9 +409,7 @@ __global__ void __launch_bounds__(kBlock) k_ct(Geo G, Region R, const double *__
     __shared__ double sEL[NL], sER[NL], sQa[NL];
 
     const int tid = threadIdx.x;
-    unsigned bx, by, bz;
-    xcd_block(bx, by, bz);
-    const int org[3] = {R.lo[0] + (int)bx * T0, R.lo[1] + (int)by * T1, R.lo[2] + (int)bz * T2};
+    const int org[3] = {R.lo[0] + (int)blk.x * T0, R.lo[1] + (int)blk.y * T1, R.lo[2] + (int)blk.z * T2};
     const bool actA = G.act[A], actB = G.act[B];
 
     // ---- step 1: a-face states of psi^4 E_k and q_B^a, clamped into range
@@ -447,7 +499,19 @@ __global__ void __launch_bounds__(kBlock) k_ct(Geo G, Region R, const double *__
         }
         ae = sm / na;
     }
-    stb(EM, o, ae * 0.25 * (ELL + ELR + ERL + ERR) + 0.5 * ca * (qbR - qbL) - 0.5 * cb * (qaR - qaL));
+    stb(args.EM, o, ae * 0.25 * (ELL + ELR + ERL + ERR) + 0.5 * ca * (qbR - qbL) - 0.5 * cb * (qaR - qaL));
+}
+template <int REC, int MET, int K>
+__global__ void __launch_bounds__(kBlock) k_ct(CtArgs a)
+{
+    ct_body<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
+}
+template <int REC, int MET, int K>
+__global__ void __launch_bounds__(kBlock) kb_ct(const CtArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
+{
+    unsigned lb;
+    const CtArgs &a = aa[batch_locate<true>(start, n, lb)];
+    ct_body<REC, MET, K>(a, blk_of(lb, a.gd));
 }
 
 // ---------------------------------------------------------------------------
@@ -465,11 +529,24 @@ struct FaceLs {
     const double *Lf[4][3];  // stored face L of stage j, direction d (may be null)
     double *Lst[3];          // where this pass stores its face L (withL)
 };
-__global__ void __launch_bounds__(kBlock) k_face_update(Geo G, Region R, StageArgs A, CPtr<3> EM, CPtr<3> fn,
-                                                        FaceLs Ls, Ptr<3> fout)
+struct FaceArgs {
+    Geo G;
+    Region R;
+    StageArgs A;
+    CPtr<3> EM, fn;
+    FaceLs Ls;
+    Ptr<3> fout;
+    GridDims gd;
+};
+__device__ __forceinline__ void face_body(const FaceArgs &a, Blk blk)
 {
+    const Geo &G = a.G;
+    const StageArgs &A = a.A;
+    const CPtr<3> &EM = a.EM, &fn = a.fn;
+    const FaceLs &Ls = a.Ls;
+    const Ptr<3> &fout = a.fout;
     int c[3];
-    if (!region_point(R, c)) return;
+    if (!region_point(a.R, blk, c)) return;
     bool in[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) in[d] = c[d] < G.g[d] + G.n[d];
@@ -494,6 +571,14 @@ __global__ void __launch_bounds__(kBlock) k_face_update(Geo G, Region R, StageAr
         }
         stb(fout.p[d], o, acc);
     }
+}
+__global__ void __launch_bounds__(kBlock) k_face_update(FaceArgs a) { face_body(a, blk_of(hw_linear<false>(), a.gd)); }
+__global__ void __launch_bounds__(kBlock)
+    kb_face_update(const FaceArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
+{
+    unsigned lb;
+    const FaceArgs &a = aa[batch_locate<false>(start, n, lb)];
+    face_body(a, blk_of(lb, a.gd));
 }
 
 // ---------------------------------------------------------------------------
@@ -524,16 +609,27 @@ __device__ __forceinline__ double bcc_dev(const Geo &G, const double *const *fac
 // cell pass.  SWZ: the z phase of the explicit operator runs first on a
 // TX x 1 x TZ tile (one thread per cell), the other variants take one cell per
 // thread over the interior.
+struct CellArgs {
+    Geo G;
+    Phys P;
+    Region R;
+    StageArgs A;
+    CellIO io;
+    GridDims gd;
+};
 template <int REC, int MET, int SWZ, int TX, int TZ>
-__global__ void __launch_bounds__(kBlock) k_cell_update(Geo G, Phys P, Region R, StageArgs A, CellIO io)
+__device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
 {
+    const Geo &G = args.G;
+    const Phys &P = args.P;
+    const Region &R = args.R;
+    const StageArgs &A = args.A;
+    const CellIO &io = args.io;
     int c[3];
     double Lz[8];
     if (SWZ) {
         __shared__ double lds[SWZ ? PhaseDims<2, TX, 1, TZ>::LDS : 1];
-        unsigned bx, by, bz;
-        xcd_block(bx, by, bz);
-        const int org[3] = {R.lo[0] + (int)bx * TX, R.lo[1] + (int)by, R.lo[2] + (int)bz * TZ};
+        const int org[3] = {R.lo[0] + (int)blk.x * TX, R.lo[1] + (int)blk.y, R.lo[2] + (int)blk.z * TZ};
         CPtr<8> sp;
         CPtr<3> sf;
         CPtr<2> met;
@@ -549,7 +645,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_update(Geo G, Phys P, Region R,
         c[2] = org[2] + (int)threadIdx.x / TX;
         if (c[0] >= R.lo[0] + R.cnt[0] || c[2] >= R.lo[2] + R.cnt[2]) return;
     } else {
-        if (!region_point(R, c)) return;
+        if (!region_point(R, blk, c)) return;
     }
     const unsigned o = (unsigned)lin(G, c) << 3;
     double al = 1.0, ps = 1.0;
@@ -745,6 +841,19 @@ __global__ void __launch_bounds__(kBlock) k_cell_update(Geo G, Phys P, Region R,
         stb(io.out[4], o, pr);
     }
     if (status == 2) atomicAdd(io.nfail, 1ull);
+}
+template <int REC, int MET, int SWZ, int TX, int TZ>
+__global__ void __launch_bounds__(kBlock) k_cell_update(CellArgs a)
+{
+    cell_body<REC, MET, SWZ, TX, TZ>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
+}
+template <int REC, int MET, int SWZ, int TX, int TZ>
+__global__ void __launch_bounds__(kBlock)
+    kb_cell_update(const CellArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
+{
+    unsigned lb;
+    const CellArgs &a = aa[batch_locate<SWZ != 0>(start, n, lb)];
+    cell_body<REC, MET, SWZ, TX, TZ>(a, blk_of(lb, a.gd));
 }
 
 }  // namespace gr

@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libgrmhd.so")
 GR_OK, GR_EINVAL, GR_ENOMEM, GR_EHIP, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
 EXPORTED = ["gr_abi_version", "gr_strerror", "gr_validate", "gr_field_stride", "gr_workspace_bytes",
             "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim", "gr_divB_norm",
-            "gr_cfl_dt", "gr_fail_count", "gr_timing_start", "gr_timing_read", "gr_kernel_class_name"]
+            "gr_cfl_dt", "gr_fail_count", "gr_timing_start", "gr_timing_read", "gr_kernel_class_name",
+            "gr_batch_create", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run", "gr_batch_stats", "gr_batch_tiles",
+            "gr_tile_name", "gr_batch_destroy"]
 
 
 class GrError(RuntimeError):
@@ -73,6 +75,19 @@ def lib():
         L.gr_timing_read.argtypes = [ctypes.c_int, D, ctypes.POINTER(ctypes.c_long), D]
         L.gr_kernel_class_name.argtypes = [ctypes.c_int]
         L.gr_kernel_class_name.restype = ctypes.c_char_p
+        PB = ctypes.POINTER(ctypes.c_void_p)
+        L.gr_batch_create.argtypes = [PB, G, S, D, ctypes.c_int, ctypes.c_char_p, V]
+        L.gr_batch_set_dt.argtypes = [V, D, V]
+        L.gr_batch_step.argtypes = [V, V]
+        L.gr_batch_run.argtypes = [V, ctypes.c_int, V]
+        L.gr_batch_stats.argtypes = [V, ctypes.POINTER(ctypes.c_int), D, ctypes.POINTER(ctypes.c_long)]
+        L.gr_batch_tiles.argtypes = [V, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.gr_tile_name.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.gr_tile_name.restype = ctypes.c_char_p
+        L.gr_batch_destroy.argtypes = [V]
+        for name in ("gr_batch_create", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run", "gr_batch_stats",
+                     "gr_batch_tiles", "gr_batch_destroy"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("gr_timing_start", "gr_timing_read", "gr_validate", "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim",
                      "gr_divB_norm", "gr_cfl_dt", "gr_fail_count"):
             getattr(L, name).restype = ctypes.c_int
@@ -164,6 +179,49 @@ def gr_timing_read(kernel_class):
 
 def gr_kernel_class_name(kernel_class):
     return lib().gr_kernel_class_name(kernel_class).decode()
+
+
+def gr_batch_create(grids, states, dt, tune_cache, stream):
+    n = len(grids)
+    ga = (gr_grid * n)(*grids)
+    sa = (gr_state * n)(*states)
+    da = (ctypes.c_double * n)(*[float(x) for x in dt])
+    h = ctypes.c_void_p()
+    tc = None if tune_cache is None else tune_cache.encode()
+    _chk(lib().gr_batch_create(ctypes.byref(h), ga, sa, da, n, tc, stream))
+    return h
+
+
+def gr_batch_set_dt(batch, dt, stream):
+    da = (ctypes.c_double * len(dt))(*[float(x) for x in dt])
+    _chk(lib().gr_batch_set_dt(batch, da, stream))
+
+
+def gr_batch_step(batch, stream):
+    _chk(lib().gr_batch_step(batch, stream))
+
+
+def gr_batch_run(batch, nsteps, stream):
+    _chk(lib().gr_batch_run(batch, int(nsteps), stream))
+
+
+def gr_batch_stats(batch):
+    n = ctypes.c_int()
+    by = ctypes.c_double()
+    c = ctypes.c_long()
+    _chk(lib().gr_batch_stats(batch, ctypes.byref(n), ctypes.byref(by), ctypes.byref(c)))
+    return n.value, by.value, c.value
+
+
+def gr_batch_tiles(batch, run):
+    a = ctypes.c_int()
+    b = ctypes.c_int()
+    _chk(lib().gr_batch_tiles(batch, run, ctypes.byref(a), ctypes.byref(b)))
+    return lib().gr_tile_name(0, a.value).decode(), lib().gr_tile_name(1, b.value).decode()
+
+
+def gr_batch_destroy(batch):
+    _chk(lib().gr_batch_destroy(batch))
 
 
 # ---------------------------------------------------------------------------
@@ -281,3 +339,45 @@ class Run:
         off = gr_workspace_offset(self.grid, kind, stage, field) // 8
         self.stream.synchronize()
         return self.work[off: off + self.np].cpu().numpy().reshape(self.setup.shape)
+
+
+class Batch:
+    """Many independent Runs advanced together (gr_batch_*).  The runs keep
+    their own device state; the batch holds the launch list of one step."""
+
+    def __init__(self, runs, dts, tune_cache=None, stream=None):
+        if not runs:
+            raise ValueError("empty batch")
+        self.runs = list(runs)
+        self.dts = [float(x) for x in dts]
+        self.stream = stream if stream is not None else runs[0].stream
+        self.h = gr_batch_create([r.grid for r in self.runs], [r.state for r in self.runs], self.dts, tune_cache,
+                                 self.stream.cuda_stream)
+
+    def step(self):
+        gr_batch_step(self.h, self.stream.cuda_stream)
+        for r, dt in zip(self.runs, self.dts):
+            r.t += dt
+
+    def run(self, nsteps):
+        gr_batch_run(self.h, nsteps, self.stream.cuda_stream)
+        for r, dt in zip(self.runs, self.dts):
+            r.t += nsteps * dt
+
+    def stats(self):
+        return gr_batch_stats(self.h)
+
+    def tiles(self, i):
+        return gr_batch_tiles(self.h, i)
+
+    def close(self):
+        if self.h is not None:
+            self.stream.synchronize()
+            gr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

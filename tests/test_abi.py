@@ -75,3 +75,35 @@ def test_strerror():
     assert L.gr_strerror(0) == b"ok"
     assert L.gr_strerror(-2) == b"workspace too small"
     assert ctypes.sizeof(grmhd.gr_grid) > 0
+
+
+def test_batch_create_rejects_bad_arguments():
+    """host-side checks of gr_batch_create, made before any device call"""
+    s1, s2 = W.shock_tube(64), W.blast_wave(16)  # IMEX-SSP2 and IMEX-SSP3
+    g1, g2 = grmhd.grid_of(s1), grmhd.grid_of(s2)
+    fake = 1 << 20
+
+    def state(g):
+        st = grmhd.gr_state()
+        st.q = st.face = st.prim = st.work = fake
+        st.work_bytes = grmhd.gr_workspace_bytes(g)
+        return st
+
+    h = ctypes.c_void_p()
+    L = grmhd.lib()
+    ga = (grmhd.gr_grid * 2)(g1, g2)
+    sa = (grmhd.gr_state * 2)(state(g1), state(g2))
+    da = (ctypes.c_double * 2)(1e-3, 1e-3)
+    assert L.gr_batch_create(ctypes.byref(h), ga, sa, da, 0, None, None) == grmhd.GR_EINVAL
+    assert L.gr_batch_create(ctypes.byref(h), ga, sa, da, 2, None, None) == grmhd.GR_EUNSUPPORTED
+    bad = (ctypes.c_double * 2)(1e-3, 0.0)
+    g2b = grmhd.grid_of(W.blast_wave(16, imex=W.SSP2))
+    ga2 = (grmhd.gr_grid * 2)(g1, g2b)
+    sa2 = (grmhd.gr_state * 2)(state(g1), state(g2b))
+    assert L.gr_batch_create(ctypes.byref(h), ga2, sa2, bad, 2, None, None) == grmhd.GR_EINVAL
+    small = state(g1)
+    small.work_bytes = 8
+    sa3 = (grmhd.gr_state * 1)(small)
+    assert L.gr_batch_create(ctypes.byref(h), ga, sa3, da, 1, None, None) == grmhd.GR_ENOMEM
+    assert h.value is None
+    assert L.gr_batch_destroy(None) == grmhd.GR_OK

@@ -1,0 +1,154 @@
+"""Batched runs (gr_batch_*) through the C ABI.
+
+A run advanced inside a batch must give the same result as the same run
+advanced alone with gr_step: every cell of a run is computed by the same
+arithmetic whatever the batch holds, so the comparison is exact.  The batch
+mixes dimensions, reconstructions, sizes, resistivities and (with the star)
+the metric; one run is checked against the CPU oracle as well.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _mix(imex):
+    """small runs of every kind the kernels distinguish"""
+    prm = W.batch_mix_params(6, seed=3, n1=(100, 700), n2=(40, 90))
+    setups = [W.make_run_setup(p, imex=imex) for p in prm]
+    setups.append(W.tov_star(20, imex=imex))
+    setups.append(W.current_sheet(96, recon=W.MC, imex=imex))
+    return setups
+
+
+def _same(a, b):
+    for x, y, what in ((a.prims(), b.prims(), "prim"), (a.faces(), b.faces(), "face"), (a.cons(), b.cons(), "cons")):
+        assert np.array_equal(x, y), what
+
+
+@pytest.mark.parametrize("imex", [W.SSP2, W.SSP3])
+def test_batch_equals_single_runs(imex):
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd
+    setups = _mix(imex)
+    say("batch of %d runs, imex %d" % (len(setups), imex))
+    alone = [grmhd.Run(s, device="cuda:0") for s in setups]
+    mixed = [grmhd.Run(s, device="cuda:0") for s in setups]
+    dts = [r.dt() for r in alone]
+    nsteps = 4
+    for r, dt in zip(alone, dts):
+        for _ in range(nsteps):
+            r.step(dt)
+    b = grmhd.Batch(mixed, dts)
+    for _ in range(nsteps):
+        b.step()
+    torch.cuda.synchronize()
+    for r1, r2, s in zip(alone, mixed, setups):
+        _same(r1, r2)
+        assert r1.fail_count() == r2.fail_count()
+    b.close()
+
+
+def test_batch_graph_replays_equal_eager():
+    """graph replays, with eager work and synchronisations between them, give
+    the eager steps' results after every replay"""
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd
+    setups = _mix(W.SSP3)
+    say("graph replay, %d runs" % len(setups))
+    ra = [grmhd.Run(s, device="cuda:0") for s in setups]
+    rb = [grmhd.Run(s, device="cuda:0") for s in setups]
+    dts = [r.dt() for r in ra]
+    ba = grmhd.Batch(ra, dts)
+    bb = grmhd.Batch(rb, dts)
+    for rep in range(3):
+        ba.step()
+        ba.step()
+        bb.run(2)
+        junk = torch.ones(1 << 20, dtype=torch.float64, device="cuda:0") * 3.0  # eager work in between
+        torch.cuda.synchronize()
+        assert float(junk.sum()) == 3.0 * (1 << 20)
+        for x, y in zip(ra, rb):
+            _same(x, y)
+    ba.close()
+    bb.close()
+
+
+def test_batch_run_matches_oracle():
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd
+    s1 = W.blast_wave(48, eta=1e-2, imex=W.SSP2)
+    s2 = W.shock_tube(300, eta=1e-3)
+    runs = [grmhd.Run(s, device="cuda:0") for s in (s1, s2)]
+    dts = [r.dt() for r in runs]
+    b = grmhd.Batch(runs, dts)
+    b.run(3)
+    torch.cuda.synchronize()
+    for s, r, dt in zip((s1, s2), runs, dts):
+        ref = oracle.OracleState(s)
+        for _ in range(3):
+            ref.step(dt)
+        got = r.prims()
+        sl = s.interior
+        for v in range(5):
+            a, c = got[v][sl], ref.prim[v][sl]
+            sc = 1.0 if v in (1, 2, 3) else max(np.abs(s.prim[v][sl]).max(), 1e-6 * np.abs(s.prim[0][sl]).max())
+            assert np.abs(a - c).sum() / max(np.abs(c).sum(), c.size * sc) <= 1e-10, (s.name, v)
+    b.close()
+
+
+def test_batch_autotuner_cache(tmp_path):
+    """the tuner writes one decision per class of runs, picks allowed tiles,
+    and a second batch reads the cache instead of timing again"""
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd
+    setups = _mix(W.SSP3)
+    runs = [grmhd.Run(s, device="cuda:0") for s in setups]
+    dts = [r.dt() for r in runs]
+    cache = str(tmp_path / "tiles.txt")
+    b = grmhd.Batch(runs, dts, tune_cache=cache)
+    lines = open(cache).read().split("\n")
+    lines = [l for l in lines if l.strip()]
+    classes = {(s.recon, s.metric, s.ndim) for s in setups}
+    assert len([l for l in lines if l.startswith("xy")]) == len(classes)
+    assert len([l for l in lines if l.startswith("cz")]) == len({c for c in classes if c[2] == 3})
+    for i, s in enumerate(setups):
+        xy, cz = b.tiles(i)
+        if s.ndim == 1:
+            assert xy.endswith("x1")
+        else:
+            assert not xy.endswith("x1")
+    # tuning launches leave no trace in the results or the failure counters
+    ref = [grmhd.Run(s, device="cuda:0") for s in setups]
+    b.step()
+    for r, dt in zip(ref, dts):
+        r.step(dt)
+    torch.cuda.synchronize()
+    for x, y in zip(runs, ref):
+        _same(x, y)
+        assert x.fail_count() == y.fail_count()
+    before = open(cache).read()
+    b2 = grmhd.Batch([grmhd.Run(s, device="cuda:0") for s in setups], dts, tune_cache=cache)
+    assert open(cache).read() == before
+    for i in range(len(setups)):
+        assert b2.tiles(i) == b.tiles(i)
+    b.close()
+    b2.close()

@@ -180,20 +180,22 @@ def _bc(ndim, kind):
 
 # ----------------------------------------------------------------------------
 # workloads of the benchmark configurations
-def shock_tube(n=400, seed=1, eta=1e-3, recon=MINMOD, imex=SSP2, noise=1e-6):
+def shock_tube(n=400, seed=1, eta=1e-3, recon=MINMOD, imex=SSP2, noise=1e-6, rho_l=1.0, rho_r=0.125, p_l=1.0,
+               p_r=0.1, by_l=0.5, bx=0.5):
     """1-D relativistic resistive shock tube (Balsara-1 type), Gamma = 2.
-    left (rho, p, Bx, By) = (1, 1, 0.5, 0.5), right (0.125, 0.1, 0.5, -0.5)."""
+    left (rho, p, Bx, By) = (1, 1, 0.5, 0.5), right (0.125, 0.1, 0.5, -0.5)
+    by default; By on the right is -By on the left."""
     s = _blank(Setup("shock_tube", 1, (n, 1, 1), 3 if recon == PPM else 2, (-0.5, 0, 0), (0.5, 1, 1),
                      _bc(1, OUTFLOW), 2.0, recon, imex, eta=eta, rho_atm=1e-12, p_atm=1e-14,
                      steps=int(round(0.4 / (0.4 * 1.0 / n)))))
     X, _, _ = s.mesh()
     left = X < 0.0
     u = uniform_pm1(seed, 0, int(np.prod(s.shape))).reshape(s.shape)
-    s.prim[0] = np.where(left, 1.0, 0.125) * (1.0 + noise * u)
-    s.prim[4] = np.where(left, 1.0, 0.1)
+    s.prim[0] = np.where(left, rho_l, rho_r) * (1.0 + noise * u)
+    s.prim[4] = np.where(left, p_l, p_r)
     face = np.zeros((3,) + s.shape)
-    face[0] = 0.5
-    face[1] = np.where(left, 0.5, -0.5)
+    face[0] = bx
+    face[1] = np.where(left, by_l, -by_l)
     s.face = face
     return s
 
@@ -511,3 +513,77 @@ def random_states(shape3, seed=1, wmax=10.0, sigma_max=10.0, emax_frac=0.5, rho_
         s.E[d] = emax_frac * bmag * U(11 + d) / math.sqrt(3)
     s.face = face
     return s
+
+
+# ---------------------------------------------------------------------------
+# many-run workloads: a batch of independent runs and a served request trace
+def _u01(seed, stream, count):
+    return 0.5 * (uniform_pm1(seed, stream, count) + 1.0)
+
+
+def _log_uniform(u, lo, hi):
+    return np.exp(np.log(lo) + u * (np.log(hi) - np.log(lo)))
+
+
+def batch_mix_params(nruns=256, seed=1, n1=(128, 4096), n2=(64, 256), eta=(1e-6, 1.0)):
+    """Parameters of a mix of independent runs: kind ~ Bernoulli(1/2); 1-D
+    shock tubes with N ~ U{n1}, rho_L ~ U[0.125, 1], rho_R ~ U[0.125, rho_L],
+    p_L ~ U[0.1, 1], p_R ~ U[0.1, p_L], By_L ~ U[-0.5, 0.5], Bx = 0.5, minmod;
+    2-D blast waves with side ~ U{n2}, p_in ~ logU[1e-2, 1], p_out = 1e-3,
+    Bx ~ U[0, 0.1], PPM; eta ~ logU[eta]; IMEX-SSP2(2,2,2) for all.  Every
+    draw comes from the counter-based generator (stream 100 + k)."""
+    u = [_u01(seed, 100 + k, nruns) for k in range(8)]
+    out = []
+    for i in range(nruns):
+        e = float(_log_uniform(u[1][i], *eta))
+        if u[0][i] < 0.5:
+            n = int(n1[0] + min(int(u[2][i] * (n1[1] - n1[0] + 1)), n1[1] - n1[0]))
+            rho_l = 0.125 + u[3][i] * (1.0 - 0.125)
+            rho_r = 0.125 + u[4][i] * (rho_l - 0.125)
+            p_l = 0.1 + u[5][i] * 0.9
+            p_r = 0.1 + u[6][i] * (p_l - 0.1)
+            by_l = -0.5 + u[7][i]
+            out.append(dict(kind="shock_tube", n=n, eta=e, rho_l=rho_l, rho_r=rho_r, p_l=p_l, p_r=p_r,
+                            by_l=by_l, seed=seed + i))
+        else:
+            n = int(n2[0] + min(int(u[2][i] * (n2[1] - n2[0] + 1)), n2[1] - n2[0]))
+            p_in = float(_log_uniform(u[3][i], 1e-2, 1.0))
+            bx = 0.1 * u[4][i]
+            out.append(dict(kind="blast_wave", n=n, eta=e, p_in=p_in, bx=bx, seed=seed + i))
+    return out
+
+
+def make_run_setup(prm, imex=SSP2):
+    """Setup of one entry of batch_mix_params / served_trace"""
+    k = prm["kind"]
+    if k == "shock_tube":
+        return shock_tube(prm["n"], seed=prm["seed"], eta=prm["eta"], recon=MINMOD, imex=imex, rho_l=prm["rho_l"],
+                          rho_r=prm["rho_r"], p_l=prm["p_l"], p_r=prm["p_r"], by_l=prm["by_l"])
+    if k == "blast_wave":
+        return blast_wave(prm["n"], eta=prm["eta"], seed=prm["seed"], recon=PPM, imex=imex,
+                          p_in=prm.get("p_in", 1.0), bx=prm.get("bx", 0.1))
+    if k == "tov_star":
+        return tov_star(prm["n"], imex=imex, eta_in=prm["eta"])
+    raise ValueError(k)
+
+
+def served_trace(nreq=2000, rate=200.0, seed=7, blast=(64, 512), star=(32, 96), steps=(10, 500), eta=(1e-6, 1.0)):
+    """Poisson request stream: exponential inter-arrival times of mean 1/rate;
+    half 2-D blast waves (side ~ U{blast}, PPM + SSP3) and half 3-D stars
+    (side ~ U{star}, PPM + SSP3, eta ~ logU[eta] inside the star); steps ~
+    U{steps}."""
+    u = [_u01(seed, 200 + k, nreq) for k in range(5)]
+    t = np.cumsum(-np.log(1.0 - u[0]) / rate)
+    out = []
+    for i in range(nreq):
+        e = float(_log_uniform(u[2][i], *eta))
+        ns = int(steps[0] + min(int(u[3][i] * (steps[1] - steps[0] + 1)), steps[1] - steps[0]))
+        if u[1][i] < 0.5:
+            n = int(blast[0] + min(int(u[4][i] * (blast[1] - blast[0] + 1)), blast[1] - blast[0]))
+            prm = dict(kind="blast_wave", n=n, eta=e, seed=seed + i)
+        else:
+            n = int(star[0] + min(int(u[4][i] * (star[1] - star[0] + 1)), star[1] - star[0]))
+            prm = dict(kind="tov_star", n=n, eta=e, seed=seed + i)
+        prm.update(rid=i, arrival=float(t[i]), steps=ns)
+        out.append(prm)
+    return out
