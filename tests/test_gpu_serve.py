@@ -1,0 +1,47 @@
+"""Continuous-batching request loop: every request's result is the same
+alone and in the mix (exactly: the kernels compute a run's cells with the
+same arithmetic whatever else the batch holds), under an HBM budget small
+enough that requests queue, join and leave the batch at different times."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def test_served_equals_alone():
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd, serve
+    trace = W.served_trace(10, rate=400.0, seed=11, blast=(24, 56), star=(14, 22), steps=(2, 9))
+    payloads = {r["rid"]: W.make_run_setup(r, imex=W.SSP3) for r in trace}
+    biggest = max(serve.run_bytes(grmhd.grid_of(s)) for s in payloads.values())
+    budget = 3 * biggest
+    print("trace of %d requests, budget %d bytes" % (len(trace), budget), flush=True)
+    srv = serve.Server(budget, chunk=3, keep=True)
+    recs, summary = srv.serve(trace, lambda r: payloads[r["rid"]])
+    assert summary["requests"] == len(trace)
+    assert summary["peak_resident_bytes"] <= budget
+    assert summary["p50_latency_s"] is not None and summary["p99_latency_s"] >= summary["p50_latency_s"]
+    assert len({r["admit"] for r in recs}) > 1  # requests joined at different times
+    for rec in recs:
+        req = trace[rec["rid"]]
+        s = payloads[rec["rid"]]
+        run = grmhd.Run(s, device="cuda:0")
+        dt = run.dt()
+        for _ in range(req["steps"]):
+            run.step(dt)
+        torch.cuda.synchronize()
+        assert np.array_equal(run.prims(), rec["prims"]), rec["rid"]
+        assert np.array_equal(run.faces(), rec["faces"]), rec["rid"]
+        assert run.fail_count() == rec["fails"]
+        assert rec["latency"] > 0.0 and rec["done"] >= rec["admit"] >= rec["arrival"] - 1e-9
