@@ -66,6 +66,110 @@ def kernel_roofline(run, dt, steps, grmhd, torch):
             "alg_GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)} for k, v in per.items()}
 
 
+def batched_vs_plain(torch, W, grmhd, nruns, steps, seed=1):
+    """The mix of independent runs (1-D shock tubes N in 128..4096 with
+    minmod, 2-D blast waves 64^2..256^2 with PPM, eta log-uniform in
+    [1e-6, 1], IMEX-SSP2, each run its own dt), `steps` steps each: plain
+    per-run launches one run after another on one stream and spread over 8
+    streams, against the batch (tiles from the autotuner) launched eagerly and
+    as one captured graph per step."""
+    prm = W.batch_mix_params(nruns, seed=seed)
+    setups = [W.make_run_setup(p, imex=W.SSP2) for p in prm]
+    zc = float(sum(s.ncells for s in setups)) * steps
+    out = {"runs": nruns, "steps": steps, "cells": int(sum(s.ncells for s in setups)),
+           "kinds": {"shock_tube_1d": sum(p["kind"] == "shock_tube" for p in prm),
+                     "blast_wave_2d": sum(p["kind"] == "blast_wave" for p in prm)}}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    runs = [grmhd.Run(s, device="cuda:0") for s in setups]
+    dts = [r.dt() for r in runs]
+
+    def plain_one_stream():
+        for r, dt in zip(runs, dts):
+            for _ in range(steps):
+                r.step(dt)
+    plain_one_stream_t = timed(plain_one_stream)
+    streams = [torch.cuda.Stream() for _ in range(8)]
+    runs8 = [grmhd.Run(s, device="cuda:0", stream=streams[i % 8]) for i, s in enumerate(setups)]
+
+    def plain_eight_streams():
+        for r, dt in zip(runs8, dts):
+            for _ in range(steps):
+                r.step(dt)
+    plain_eight_t = timed(plain_eight_streams)
+    del runs8
+    t0 = time.perf_counter()
+    b = grmhd.Batch(runs, dts, tune_cache="")
+    tune_s = time.perf_counter() - t0
+    launches, alg_bytes, _ = b.stats()
+    eager_t = timed(lambda: [b.step() for _ in range(steps)])
+    b.run(1)  # capture
+    graph_t = timed(lambda: b.run(steps))
+    tiles = {}
+    for i, p in enumerate(prm):
+        key = "1d" if p["kind"] == "shock_tube" else "2d"
+        tiles[key] = b.tiles(i)[0]
+    b.close()
+    out.update({
+        "plain_1stream_zone_cycles_per_s": round(zc / plain_one_stream_t, 1),
+        "plain_8streams_zone_cycles_per_s": round(zc / plain_eight_t, 1),
+        "batched_eager_zone_cycles_per_s": round(zc / eager_t, 1),
+        "batched_graph_zone_cycles_per_s": round(zc / graph_t, 1),
+        "batched_over_plain_1stream": round(plain_one_stream_t / graph_t, 2),
+        "batched_over_plain_8streams": round(plain_eight_t / graph_t, 2),
+        "batched_launches_per_step": launches,
+        "batched_alg_GBps": round(alg_bytes * steps / graph_t / 1e9, 1),
+        "autotune_s": round(tune_s, 3), "tiles": tiles})
+    return out
+
+
+def served(torch, W, grmhd, nreq, rate, budgets_gib, seed=7):
+    """Poisson stream of 2-D blast waves (64^2..512^2) and 3-D stars
+    (32^3..96^3), PPM + IMEX-SSP3, 10..500 steps, eta log-uniform; the
+    requests' initial data is built before the clock starts (it arrives with
+    the request).  For each HBM budget: the continuous-batching loop; then the
+    same requests one after another through the plain path."""
+    from paper_2110_03732_amd import serve
+    trace = W.served_trace(nreq, rate=rate, seed=seed)
+    cache = {}
+
+    def payload(req):
+        if req["rid"] not in cache:
+            cache[req["rid"]] = W.make_run_setup(req, imex=W.SSP3)
+        return cache[req["rid"]]
+    for r in trace:
+        payload(r)
+    out = {"requests": nreq, "rate_per_s": rate,
+           "mix": {"blast_wave_2d": sum(r["kind"] == "blast_wave" for r in trace),
+                   "tov_star_3d": sum(r["kind"] == "tov_star" for r in trace)}}
+    for gib in budgets_gib:
+        srv = serve.Server(int(gib * (1 << 30)), chunk=4)
+        recs, summ = srv.serve(trace, payload)
+        out["budget_%gGiB" % gib] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+    # plain path, requests back to back
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    zc = 0.0
+    for r in trace:
+        s = payload(r)
+        run = grmhd.Run(s, device="cuda:0")
+        dt = run.dt()
+        for _ in range(r["steps"]):
+            run.step(dt)
+        zc += s.ncells * r["steps"]
+        del run
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["plain_sequential_zone_cycles_per_s"] = round(zc / el, 1)
+    return out
+
+
 def cpu_baseline(setup_fn):
     import oracle
     s = setup_fn()
@@ -88,6 +192,10 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="cells per direction of the star workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="star workload only (no 2-D point, no roofline replay)")
+    ap.add_argument("--batch-runs", type=int, default=256, help="runs in the batched-vs-plain comparison")
+    ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--serve-requests", type=int, default=160)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--copy-ref", action="store_true",
                     help="end with a plain 256 MiB device copy, the reference kernel for scaling HBM counters")
     args = ap.parse_args()
@@ -128,6 +236,11 @@ def main():
         msb = time_steps(rb, dtb, args.steps, torch)
         extra.update({"blast_512sq_ssp3_zone_cycles_per_s": round(sb.ncells * args.steps / (msb * 1e-3), 1),
                       "blast_512sq_ms_per_step": round(msb / args.steps, 4), "per_kernel": per_kernel})
+        del rb
+        print("bench: batched vs plain", file=sys.stderr, flush=True)
+        extra["batched"] = batched_vs_plain(torch, W, grmhd, args.batch_runs, args.batch_steps)
+        print("bench: served", file=sys.stderr, flush=True)
+        extra["served"] = served(torch, W, grmhd, args.serve_requests, args.serve_rate, (32.0, 2.0))
     if args.copy_ref:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
         b = torch.empty_like(a)
