@@ -38,6 +38,28 @@ def time_steps(run, dt, steps, torch):
     return e0.elapsed_time(e1)
 
 
+def csrc_digest():
+    """first 16 hex digits of the SHA-256 of the kernel sources"""
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2110_03732_amd", "csrc", "*")))
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in files)).hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken"""
+    import glob
+    import re
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*hbm_traffic.md")):
+        txt = open(f).read()
+        m = re.search(r"csrc-sha256-16: ([0-9a-f]+)", txt)
+        t = re.search(r"traffic-bytes-per-launch %s: ([0-9.]+)" % re.escape(kernel), txt)
+        if m and t and m.group(1) == csrc_digest():
+            return float(t.group(1))
+    return None
+
+
 def kernel_roofline(run, dt, steps, grmhd, torch):
     """replay of the timed steps with every kernel class bracketed by HIP
     events on the run's stream; roofline of the class with the largest time"""
@@ -60,7 +82,7 @@ def kernel_roofline(run, dt, steps, grmhd, torch):
     achieved = by / (ms * 1e-3) / 1e9
     return name, {
         "bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(name), "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
         "avg_launch_us": round(ms * 1e3 / n, 2), "launches": n, "alg_bytes_per_launch": by / n,
     }, {k: {"ms_per_step": round(v[0] / steps, 4), "launches_per_step": v[1] / steps,
             "alg_GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)} for k, v in per.items()}
