@@ -214,6 +214,7 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="cells per direction of the star workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="star workload only (no 2-D point, no roofline replay)")
+    ap.add_argument("--no-many", action="store_true", help="skip the batched and served comparisons")
     ap.add_argument("--batch-runs", type=int, default=256, help="runs in the batched-vs-plain comparison")
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=160)
@@ -259,6 +260,7 @@ def main():
         extra.update({"blast_512sq_ssp3_zone_cycles_per_s": round(sb.ncells * args.steps / (msb * 1e-3), 1),
                       "blast_512sq_ms_per_step": round(msb / args.steps, 4), "per_kernel": per_kernel})
         del rb
+    if not args.no_extra and not args.no_many:
         print("bench: batched vs plain", file=sys.stderr, flush=True)
         extra["batched"] = batched_vs_plain(torch, W, grmhd, args.batch_runs, args.batch_steps)
         print("bench: served", file=sys.stderr, flush=True)
