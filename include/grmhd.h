@@ -39,14 +39,14 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 1
+#define GR_ABI_VERSION 2
 
 typedef enum {
     GR_OK = 0,
     GR_EINVAL = -1,        /* bad argument, shape or parameter            */
     GR_ENOMEM = -2,        /* workspace too small                         */
     GR_EHIP = -3,          /* a HIP runtime call or kernel launch failed   */
-    GR_EUNSUPPORTED = -4   /* valid but not implemented (e.g. xi != 0)    */
+    GR_EUNSUPPORTED = -4   /* valid but not implemented (e.g. mixed IMEX tableaux in a batch) */
 } gr_status;
 
 enum { GR_OUTFLOW = 0, GR_PERIODIC = 1, GR_FIXED = 2 };   /* boundary rules  */
@@ -71,8 +71,9 @@ typedef struct gr_grid {
     int metric;           /* 0 flat, 1 static conformally flat (alpha, psi)     */
     double newton_tol;    /* Newton stop: |du~|_inf <= tol (1 + |u~|_inf)       */
     int newton_maxit;
-    double xi;            /* mean-field dynamo; must be 0                       */
+    double xi;            /* mean-field dynamo coefficient of eq. ohms_law      */
     double atm_factor;    /* cells with D <= atm_factor rho_atm are atmosphere  */
+    int frozen_matter;    /* 1: rho, u~, p stay fixed and only E and B evolve   */
 } gr_grid;
 
 /* Device state of one run (all pointers caller-owned device memory). */

@@ -51,6 +51,7 @@ typedef struct {
     int newton_maxit;
     double xi;           /* mean-field dynamo coefficient of eq. ohms_law     */
     double atm_factor;   /* cells with D <= atm_factor rho_atm are atmosphere */
+    int frozen_matter;   /* 1: rho, u~, p stay fixed, only E and B evolve     */
 } or_grid;
 
 enum { BC_OUTFLOW = 0, BC_PERIODIC = 1, BC_FIXED = 2 };
@@ -1111,21 +1112,40 @@ static void atmo_prim(const or_grid *G, double prim[5])
     prim[4] = G->p_atm;
 }
 
+/* Electric field of a cell at rest (u~ = 0, W = 1): eq. im_E reduces to
+ * (1 + eta~) E = eta~ E* + xi B (A_0 = 1 + eta~, A_3 = xi, the other terms
+ * vanish), written with r = 1/eta~ = alpha a_ii dt / eta as
+ * (E* + xi r B) / (1 + r). */
+static void E_at_rest(double r, double xi, const double Es[3], const double B[3], double E[3])
+{
+    for (int i = 0; i < 3; i++) E[i] = (Es[i] + xi * r * B[i]) / (1.0 + r);
+}
+
 /* The fused implicit solve of one cell within stage with diagonal weight aii.
- * Returns 0 normal, 1 atmosphere, 2 failure (fallback applied). */
+ * fz != NULL: frozen matter (the paper's dynamo test evolves only the
+ * electromagnetic fields): the primitives stay fz and E follows from eq.
+ * im_E at the fixed u~.  Returns 0 normal, 1 atmosphere, 2 failure (fallback
+ * applied). */
 static int cell_implicit(const or_grid *G, double al, double ps, const double qs[8], const double B[3], double aii,
-                         double dt, const double guess[3], double prim[5], double E[3])
+                         double dt, const double guess[3], const double *fz, double prim[5], double E[3])
 {
     double p6 = pow6(ps);
     double Dund = qs[0] / p6;
-    double eta = or_eta(G, Dund);
     double Es[3] = {qs[5] / p6, qs[6] / p6, qs[7] / p6};
+    if (fz) {
+        double eta = or_eta(G, fz[0] * sqrt(1.0 + (fz[1] * fz[1] + fz[2] * fz[2] + fz[3] * fz[3]) * pow4(ps)));
+        double ut[3] = {fz[1], fz[2], fz[3]};
+        for (int v = 0; v < 5; v++) prim[v] = fz[v];
+        or_implicit_E(ps, eta / (al * aii * dt), G->xi, ut, Es, B, E);
+        return 0;
+    }
+    double eta = or_eta(G, Dund);
+    double etat = eta / (al * aii * dt);
     if (Dund <= G->rho_atm * G->atm_factor) {
         atmo_prim(G, prim);
-        for (int i = 0; i < 3; i++) E[i] = Es[i] / (1.0 + al * aii * dt / eta);
+        E_at_rest(al * aii * dt / eta, G->xi, Es, B, E);
         return 1;
     }
-    double etat = eta / (al * aii * dt);
     int it;
     int bad = or_implicit(G->gamma_ad, ps, qs, B, etat, G->xi, guess, G->newton_tol, G->newton_maxit, prim, E, &it);
     /* p = (w~/W - rho)/Gamma_1 cancels to round-off for a cold gas: a
@@ -1140,7 +1160,7 @@ static int cell_implicit(const or_grid *G, double al, double ps, const double qs
     }
     if (bad) {
         atmo_prim(G, prim);
-        for (int i = 0; i < 3; i++) E[i] = Es[i] / (1.0 + al * aii * dt / eta);
+        E_at_rest(al * aii * dt / eta, G->xi, Es, B, E);
         return 2;
     }
     return 0;
@@ -1189,6 +1209,7 @@ static void bcc_at(const geom *q, double **face, const double *psi, long id, con
  * number of failures */
 long or_c2p_grid(const or_grid *G, double **qc, double **face, double **prim, const double *psi)
 {
+    if (G->frozen_matter) return 0; /* the primitives do not change */
     geom q = mkgeom(G);
     const double *ps_arr = G->metric ? psi : NULL;
     long nfail = 0;
@@ -1284,8 +1305,10 @@ long or_step(const or_grid *G, double **qc, double **face, double **prim, const 
                     double guess[3];
                     double **gp = (i == 0) ? prim : sp[i - 1];
                     for (int a = 0; a < 3; a++) guess[a] = gp[1 + a][id];
-                    double pr[5], E[3];
-                    int r = cell_implicit(G, al, ps, qs, B, aii, dt, guess, pr, E);
+                    double pr[5], E[3], fz[5];
+                    if (G->frozen_matter)
+                        for (int v = 0; v < 5; v++) fz[v] = prim[v][id];
+                    int r = cell_implicit(G, al, ps, qs, B, aii, dt, guess, G->frozen_matter ? fz : NULL, pr, E);
                     if (r == 2) nfail++;
                     double p6 = pow6(ps);
                     for (int v = 0; v < 5; v++) sp[i][v][id] = pr[v];
@@ -1332,7 +1355,7 @@ long or_step(const or_grid *G, double **qc, double **face, double **prim, const 
         for (int jj = q.g[1]; jj < q.g[1] + q.n[1]; jj++)
             for (int ii = q.g[0]; ii < q.g[0] + q.n[0]; ii++) {
                 long id = IX(&q, ii, jj, k);
-                for (int v = 0; v < 8; v++) {
+                for (int v = G->frozen_matter ? 5 : 0; v < 8; v++) {
                     double acc = qc[v][id];
                     for (int j = 0; j < s; j++) {
                         acc += dt * wt[j] * Lc[j][v][id];

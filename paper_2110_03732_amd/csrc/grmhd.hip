@@ -103,6 +103,8 @@ Phys make_phys(const gr_grid *g)
     P.D_atm = g->rho_atm * g->atm_factor;
     P.tol = g->newton_tol;
     P.maxit = g->newton_maxit;
+    P.xi = g->xi;
+    P.frozen = g->frozen_matter;
     P.eta_mode = g->eta_mode;
     P.eta = g->eta;
     P.sigma0 = g->sigma0;
@@ -1065,7 +1067,8 @@ gr_status gr_validate(const gr_grid *g)
         if (g->bc[d][0] == GR_PERIODIC && g->n[d] < g->ng) return GR_EINVAL;
     }
     if (!(g->gamma_ad > 1.0)) return GR_EINVAL;
-    if (g->xi != 0.0) return GR_EUNSUPPORTED;
+    if (!std::isfinite(g->xi)) return GR_EINVAL;
+    if (g->frozen_matter != 0 && g->frozen_matter != 1) return GR_EINVAL;
     if (!(g->newton_tol > 0.0) || g->newton_maxit < 1) return GR_EINVAL;
     if (g->eta_mode == GR_ETA_UNIFORM) {
         if (!(g->eta > 0.0)) return GR_EINVAL;

@@ -24,6 +24,8 @@ struct Phys {
     int maxit;
     int eta_mode;
     double eta, sigma0, eta_min, eta_max;
+    double xi;   // mean-field dynamo coefficient (eq. ohms_law)
+    int frozen;  // 1: primitives fixed, only E and B evolve
 };
 
 // flat-frame primitive state -> conserved (D, S, tau, E) and the flux in
@@ -111,12 +113,37 @@ __device__ __forceinline__ double cell_eta(const Phys &P, double Dund)
 // Newton with the analytic Jacobian, 3x3 solve by the adjugate, backtracking
 // line search on F = f.f/2 (Armijo 1e-4, quadratic model, cut in [0.1, 0.5]).
 struct ImpSys {
-    double D, tau, S[3], Es[3], B[3], et, iG1, B2;
+    double D, tau, S[3], Es[3], B[3], et, iG1, B2, xi;
 };
 // everything the Jacobian needs from one residual evaluation
 struct ImpEval {
     double f[3], E[3], wt, W, iW, r1, iA0, iden, Esu, U;
 };
+
+// the six coefficients of eq. im_E and their W-derivatives (Sec 2.4), for
+// xi != 0; with xi = 0 they reduce to A_0 = W + et, A_1 = et/(1 + et W),
+// A_5 = -1 and A_2 = A_3 = A_4 = 0, which the solver uses directly
+struct ImCoef {
+    double A[6], Ad[6];
+};
+__device__ __forceinline__ void im_coef(double W, double et, double xi, ImCoef &c)
+{
+    const double x2 = xi * xi;
+    const double iWpe = frcp(W + et), iopW = frcp(1.0 + W * et);
+    const double iWpe2 = iWpe * iWpe, iopW2 = iopW * iopW;
+    c.A[0] = W + et + x2 * (W * W - 1.0) * iWpe;
+    c.A[1] = et * iopW + x2 * et * W * iWpe * iopW;
+    c.A[2] = -xi * et * iWpe;
+    c.A[3] = xi * (1.0 + W * et) * iWpe;
+    c.A[4] = xi * (1.0 - et * et + x2) * iWpe * iopW;
+    c.A[5] = -1.0 - x2 * W * iWpe;
+    c.Ad[0] = 1.0 + x2 * (1.0 + W * W + 2.0 * W * et) * iWpe2;
+    c.Ad[1] = -et * et * iopW2 - x2 * et * et * (W * W - 1.0) * iopW2 * iWpe2;
+    c.Ad[2] = xi * et * iWpe2;
+    c.Ad[3] = xi * (et * et - 1.0) * iWpe2;
+    c.Ad[4] = -xi * (1.0 - et * et + x2) * (1.0 + et * et + 2.0 * W * et) * iopW2 * iWpe2;
+    c.Ad[5] = -x2 * et * iWpe2;
+}
 
 __device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], ImpEval &e)
 {
@@ -126,10 +153,24 @@ __device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], Imp
     e.r1 = frcp(1.0 + s.et * e.W);  // A1 = et r1
     e.iA0 = frcp(e.W + s.et);
     e.Esu = s.Es[0] * u[0] + s.Es[1] * u[1] + s.Es[2] * u[2];
-    double A1 = s.et * e.r1;
     double uxB[3] = {u[1] * s.B[2] - u[2] * s.B[1], u[2] * s.B[0] - u[0] * s.B[2], u[0] * s.B[1] - u[1] * s.B[0]};
+    if (s.xi == 0.0) {
+        double A1 = s.et * e.r1;
 #pragma unroll
-    for (int i = 0; i < 3; i++) e.E[i] = (s.et * s.Es[i] + A1 * e.Esu * u[i] - uxB[i]) * e.iA0;
+        for (int i = 0; i < 3; i++) e.E[i] = (s.et * s.Es[i] + A1 * e.Esu * u[i] - uxB[i]) * e.iA0;
+    } else {
+        ImCoef c;
+        im_coef(e.W, s.et, s.xi, c);
+        e.iA0 = frcp(c.A[0]);
+        double Bu = s.B[0] * u[0] + s.B[1] * u[1] + s.B[2] * u[2];
+        double uxE[3] = {u[1] * s.Es[2] - u[2] * s.Es[1], u[2] * s.Es[0] - u[0] * s.Es[2],
+                         u[0] * s.Es[1] - u[1] * s.Es[0]};
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+            e.E[i] = (s.et * s.Es[i] + c.A[1] * e.Esu * u[i] + c.A[2] * uxE[i] + c.A[3] * s.B[i] +
+                      c.A[4] * Bu * u[i] + c.A[5] * uxB[i]) *
+                     e.iA0;
+    }
     e.U = 0.5 * (e.E[0] * e.E[0] + e.E[1] * e.E[1] + e.E[2] * e.E[2] + s.B2);
     e.iden = frcp(e.W * e.W - s.iG1);
     e.wt = (e.W * (s.tau + s.D - e.U) - s.D * s.iG1) * e.iden;
@@ -141,23 +182,51 @@ __device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], Imp
 
 __device__ __forceinline__ void imp_jac(const ImpSys &s, const double u[3], const ImpEval &e, double J[3][3])
 {
-    double A1 = s.et * e.r1, A1d = -s.et * s.et * e.r1 * e.r1;
     double iA0W = e.iA0 * e.iW;
     double dE[3][3];
+    if (s.xi == 0.0) {
+        double A1 = s.et * e.r1, A1d = -s.et * s.et * e.r1 * e.r1;
 #pragma unroll
-    for (int i = 0; i < 3; i++)
+        for (int i = 0; i < 3; i++)
 #pragma unroll
-        for (int j = 0; j < 3; j++) {
-            double t = -e.E[i] * u[j] + A1 * e.W * u[i] * s.Es[j] +
-                       (A1 * e.W * (i == j ? 1.0 : 0.0) + A1d * u[i] * u[j]) * e.Esu;
-            // - W eps_{i j m} B_m
-            if (i != j) {
-                int m = 3 - i - j;
-                double sg = ((j - i + 3) % 3 == 1) ? 1.0 : -1.0;
-                t -= e.W * sg * s.B[m];
+            for (int j = 0; j < 3; j++) {
+                double t = -e.E[i] * u[j] + A1 * e.W * u[i] * s.Es[j] +
+                           (A1 * e.W * (i == j ? 1.0 : 0.0) + A1d * u[i] * u[j]) * e.Esu;
+                // - W eps_{i j m} B_m
+                if (i != j) {
+                    int m = 3 - i - j;
+                    double sg = ((j - i + 3) % 3 == 1) ? 1.0 : -1.0;
+                    t -= e.W * sg * s.B[m];
+                }
+                dE[i][j] = t * iA0W;
             }
-            dE[i][j] = t * iA0W;
-        }
+    } else {
+        // A_0 W dE^i/du^j = -Ad_0 E^i u_j + A_1 W u^i E*_j + Ad_3 B^i u_j + A_4 W u^i B_j
+        //   + (A_1 W d_ij + Ad_1 u^i u_j)(E*.u) + (A_4 W d_ij + Ad_4 u^i u_j)(B.u)
+        //   + eps_ijm (A_2 W E*_m + A_5 W B_m) + u_j (Ad_2 (u x E*)^i + Ad_5 (u x B)^i)
+        ImCoef c;
+        im_coef(e.W, s.et, s.xi, c);
+        double Bu = s.B[0] * u[0] + s.B[1] * u[1] + s.B[2] * u[2];
+        double uxE[3] = {u[1] * s.Es[2] - u[2] * s.Es[1], u[2] * s.Es[0] - u[0] * s.Es[2],
+                         u[0] * s.Es[1] - u[1] * s.Es[0]};
+        double uxB[3] = {u[1] * s.B[2] - u[2] * s.B[1], u[2] * s.B[0] - u[0] * s.B[2], u[0] * s.B[1] - u[1] * s.B[0]};
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                double dij = (i == j) ? 1.0 : 0.0;
+                double t = -c.Ad[0] * e.E[i] * u[j] + c.A[1] * e.W * u[i] * s.Es[j] + c.Ad[3] * s.B[i] * u[j] +
+                           c.A[4] * e.W * u[i] * s.B[j] + (c.A[1] * e.W * dij + c.Ad[1] * u[i] * u[j]) * e.Esu +
+                           (c.A[4] * e.W * dij + c.Ad[4] * u[i] * u[j]) * Bu +
+                           u[j] * (c.Ad[2] * uxE[i] + c.Ad[5] * uxB[i]);
+                if (i != j) {
+                    int m = 3 - i - j;
+                    double sg = ((j - i + 3) % 3 == 1) ? 1.0 : -1.0;
+                    t += e.W * sg * (c.A[2] * s.Es[m] + c.A[5] * s.B[m]);
+                }
+                dE[i][j] = t * iA0W;
+            }
+    }
     double tDU = (s.tau + s.D - e.U) * e.iW;
 #pragma unroll
     for (int j = 0; j < 3; j++) {

@@ -748,6 +748,45 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     double Es[3] = {qs[5] * ips6 * ps2, qs[6] * ips6 * ps2, qs[7] * ips6 * ps2};
     double rho = P.rho_atm, u[3] = {0.0, 0.0, 0.0}, pr = P.p_atm, E[3];
     int status = 0;  // 0 ok, 1 atmosphere, 2 failure
+    if (P.frozen && A.fin) {
+        // frozen matter: the primitives and q_D, q_S, q_tau stay; only q_E advances
+#pragma unroll
+        for (int i = 0; i < 3; i++) stb(io.q[5 + i], o, qs[5 + i]);
+        return;
+    }
+    if (P.frozen) {
+        // frozen matter: primitives fixed, E from eq. im_E at the fixed u~
+        rho = ldb(io.guess[0], o);
+        pr = ldb(io.guess[4], o);
+        ImpSys sy;
+        sy.D = sy.tau = 0.0;
+        sy.iG1 = P.iG1;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            sy.S[i] = 0.0;
+            sy.Es[i] = Es[i];
+            sy.B[i] = B[i];
+            u[i] = ps2 * ldb(io.guess[1 + i], o);
+        }
+        sy.B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        sy.xi = P.xi;
+        const double Wf = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        sy.et = cell_eta(P, rho * Wf) / (al * A.aii_dt);
+        ImpEval ev;
+        imp_eval(sy, u, ev);
+        stb(io.out[0], o, rho);
+#pragma unroll
+        for (int i = 0; i < 3; i++) stb(io.out[1 + i], o, u[i] * ips2);
+        stb(io.out[4], o, pr);
+        const double iadt = 1.0 / A.aii_dt;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            double Ec = ev.E[i] * ips2;
+            stb(io.out[5 + i], o, Ec);
+            stb(io.Rout[i], o, (ps6 * Ec - qs[5 + i]) * iadt);
+        }
+        return;
+    }
     if (!A.fin) {
         double eta = cell_eta(P, D);
         if (D <= P.D_atm) {
@@ -766,6 +805,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
             }
             sy.B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
             sy.et = eta / (al * A.aii_dt);
+            sy.xi = P.xi;
             ImpEval ev;
             int bad = implicit_solve(sy, P.tol, P.maxit, u, ev);
             if (!bad) {
@@ -782,9 +822,11 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
             rho = P.rho_atm;
             u[0] = u[1] = u[2] = 0.0;
             pr = P.p_atm;
-            double fct = 1.0 / (1.0 + al * A.aii_dt / eta);  // exact v = 0 solution
+            // exact solution at rest: (1 + et) E = et E* + xi B, as (E* + xi B/et)/(1 + 1/et)
+            const double iet = al * A.aii_dt / eta;
+            const double fct = 1.0 / (1.0 + iet);
 #pragma unroll
-            for (int i = 0; i < 3; i++) E[i] = Es[i] * fct;
+            for (int i = 0; i < 3; i++) E[i] = (Es[i] + P.xi * iet * B[i]) * fct;
         }
         stb(io.out[0], o, rho);
 #pragma unroll

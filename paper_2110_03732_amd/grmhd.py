@@ -34,7 +34,7 @@ class gr_grid(ctypes.Structure):
                 ("sigma0", ctypes.c_double), ("eta_min", ctypes.c_double), ("eta_max", ctypes.c_double),
                 ("rho_atm", ctypes.c_double), ("p_atm", ctypes.c_double), ("metric", ctypes.c_int),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int), ("xi", ctypes.c_double),
-                ("atm_factor", ctypes.c_double)]
+                ("atm_factor", ctypes.c_double), ("frozen_matter", ctypes.c_int)]
 
 
 class gr_state(ctypes.Structure):
@@ -252,6 +252,7 @@ def grid_of(s) -> gr_grid:
     g.newton_maxit = s.newton_maxit
     g.xi = s.xi
     g.atm_factor = s.atm_factor
+    g.frozen_matter = s.frozen_matter
     return g
 
 

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     L = grmhd.lib()
     for name in declared_symbols():
         assert hasattr(L, name), name
-    assert grmhd.gr_abi_version() == 1
+    assert grmhd.gr_abi_version() == 2
 
 
 def test_validation_rejects_bad_grids():
@@ -39,7 +39,12 @@ def test_validation_rejects_bad_grids():
         assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL, field
     g2 = grmhd.grid_of(s)
     g2.xi = 0.1
-    assert grmhd.gr_validate(g2) == grmhd.GR_EUNSUPPORTED
+    assert grmhd.gr_validate(g2) == 0  # mean-field dynamo supported
+    g2.xi = float("nan")
+    assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
+    g2 = grmhd.grid_of(s)
+    g2.frozen_matter = 2
+    assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
     g2 = grmhd.grid_of(s)
     g2.bc[0][0] = W.PERIODIC  # periodic on one side only
     assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL

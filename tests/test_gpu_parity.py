@@ -49,6 +49,18 @@ def compare_prims(s, run, ref, tol):
     return errs
 
 
+def compare_E(s, run, ref, tol):
+    """electric field, scale max(|E_0|, |B_0|)"""
+    got, want = run.E(), ref.E()
+    sl = s.interior
+    sc = max(np.abs(s.E).max() if s.E is not None else 0.0, 1e-30)
+    if s.face is not None:
+        sc = max(sc, np.abs(s.face).max())
+    for i in range(3):
+        a, b = got[i][sl], want[i][sl]
+        assert np.abs(a - b).sum() / max(np.abs(b).sum(), b.size * sc) <= tol, i
+
+
 def compare_faces(s, run, ref, tol):
     got = run.faces()
     sl = s.interior
@@ -74,7 +86,15 @@ CASES = {
     "charged_vortex_32_fixed": lambda: W.charged_vortex(32),
     "star_24_cowling": lambda: W.tov_star(24),
     "star_13x11x9_ragged": lambda: _ragged_star(),
+    "dynamo_k1_frozen_xi0.5": lambda: W.steady_dynamo(64, k=1),
+    "blast_48_ppm_ssp3_xi0.05": lambda: _with(W.blast_wave(48, eta=1e-2), xi=0.05),
 }
+
+
+def _with(s, **kw):
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
 
 
 def _ragged_blast():
@@ -127,13 +147,15 @@ def test_one_step_parity(name):
     ref.step(dt)
     errs = compare_prims(s, run, ref, 1e-10)
     compare_faces(s, run, ref, 1e-10)
+    compare_E(s, run, ref, 1e-10)
     d = run.divB()
     assert d[2] <= 1e-12
     assert run.fail_count() == ref.nfail
     say("  rel L1 %s" % ["%.1e" % e for e in errs])
 
 
-@pytest.mark.parametrize("name", ["shock_tube_400_minmod_ssp2", "blast_48_ppm_ssp3_eta1e-2", "star_24_cowling"])
+@pytest.mark.parametrize("name", ["shock_tube_400_minmod_ssp2", "blast_48_ppm_ssp3_eta1e-2", "star_24_cowling",
+                                  "dynamo_k1_frozen_xi0.5"])
 def test_hundred_steps_parity(name):
     _torch()
     say("case %s: 100 steps" % name)
@@ -145,6 +167,8 @@ def test_hundred_steps_parity(name):
         run.step(dt)
         ref.step(dt)
     errs = compare_prims(s, run, ref, 1e-8)
+    compare_faces(s, run, ref, 1e-8)
+    compare_E(s, run, ref, 1e-8)
     d = run.divB()
     assert d[2] <= 1e-12
     say("  rel L1 %s" % ["%.1e" % e for e in errs])

@@ -1,7 +1,9 @@
 """Continuous-batching request loop: every request's result is the same
-alone and in the mix (exactly: the kernels compute a run's cells with the
-same arithmetic whatever else the batch holds), under an HBM budget small
-enough that requests queue, join and leave the batch at different times."""
+alone and in the mix, under an HBM budget small enough that requests queue,
+join and leave the batch at different times.  Alone = the request served by
+itself (the same batched kernels: exact) and the request stepped through the
+single-grid path (separately compiled kernels: within 1e-13 of each field's
+scale)."""
 import sys
 
 import numpy as np
@@ -36,12 +38,18 @@ def test_served_equals_alone():
     for rec in recs:
         req = trace[rec["rid"]]
         s = payloads[rec["rid"]]
+        solo = serve.Server(budget, chunk=3, keep=True)
+        one, _ = solo.serve([dict(req, arrival=0.0)], lambda r: payloads[r["rid"]])
+        assert np.array_equal(one[0]["prims"], rec["prims"]), rec["rid"]
+        assert np.array_equal(one[0]["faces"], rec["faces"]), rec["rid"]
+        assert one[0]["fails"] == rec["fails"]
         run = grmhd.Run(s, device="cuda:0")
         dt = run.dt()
         for _ in range(req["steps"]):
             run.step(dt)
         torch.cuda.synchronize()
-        assert np.array_equal(run.prims(), rec["prims"]), rec["rid"]
-        assert np.array_equal(run.faces(), rec["faces"]), rec["rid"]
+        for got, want in ((run.prims(), rec["prims"]), (run.faces(), rec["faces"])):
+            for f in range(got.shape[0]):
+                assert np.abs(got[f] - want[f]).max() <= 1e-13 * max(np.abs(want[f]).max(), 1e-300), rec["rid"]
         assert run.fail_count() == rec["fails"]
         assert rec["latency"] > 0.0 and rec["done"] >= rec["admit"] >= rec["arrival"] - 1e-9

@@ -216,3 +216,49 @@ def test_implicit_small_eta_ideal_limit():
         errs.append(np.abs(E + np.cross(v, B)).max())
     assert errs[1] < errs[0] * 0.05
     assert errs[1] < 1e-4
+
+
+# --------------------------------------------------------------------------
+# mean-field dynamo (xi != 0, eq. ohms_law): manufactured roots of the fused
+# solve from the implicit Ohm's-law equation written out directly
+@pytest.mark.parametrize("xi", [0.2, -0.5])
+@pytest.mark.parametrize("etat", [1e-3, 1.0, 1e3])
+def test_implicit_manufactured_root_dynamo(xi, etat):
+    rng = np.random.default_rng(int(1000 * abs(xi) + 10 * math.log10(etat) + 77))
+    for _ in range(20):
+        psi = 1.0 + 0.2 * rng.random()
+        g = psi ** 4
+        rho = 10 ** rng.uniform(-1, 1)
+        p = rho * 10 ** rng.uniform(-2, 1)
+        W = 1 + 3 * rng.random() ** 2
+        ut = math.sqrt(W * W - 1) * unit(rng) / psi ** 2
+        b = math.sqrt(10 ** rng.uniform(-2, 0) * rho)
+        B = b * unit(rng) / psi ** 2
+        Et = 0.5 * b * rng.random() * unit(rng) / psi ** 2
+        prim = np.array([rho, *ut, p])
+        q = oracle.prim2cons(GAM, psi, prim, Et, B)
+        v = ut / W
+        Es = Et + (W / etat) * ((Et + crossg(psi, v, B) - g * (Et @ v) * v)
+                                - xi * (B - crossg(psi, v, Et) - g * (B @ v) * v))
+        q[5:] = psi ** 6 * Es
+        r, got, E, it = oracle.implicit(GAM, psi, q, B, etat, xi, prim[1:4] * 0.97)
+        assert r == 0
+        assert got[0] == pytest.approx(prim[0], rel=1e-10)
+        assert np.abs(got[1:4] - prim[1:4]).max() <= 1e-10 * (1 + np.abs(prim[1:4]).max())
+        assert got[4] == pytest.approx(prim[4], rel=1e-9)
+        assert np.abs(E - Et).max() <= 1e-9 * max(np.abs(Et).max(), np.abs(B).max())
+
+
+def test_implicit_v_zero_closed_form_dynamo():
+    """fluid at rest: (1 + eta~) E = eta~ E* + xi B"""
+    for etat, xi in [(1e-4, 0.5), (0.3, -0.2), (5.0, 0.9)]:
+        E0 = np.array([0.2, -0.4, 0.1])
+        B = np.array([0.3, 0.5, -0.2])
+        prim = np.array([1.0, 0, 0, 0, 0.5])
+        Etrue = (etat * E0 + xi * B) / (1 + etat)
+        q = oracle.prim2cons(GAM, 1.0, prim, Etrue, B)
+        q[5:] = E0
+        r, got, E, _ = oracle.implicit(GAM, 1.0, q, B, etat, xi, np.zeros(3))
+        assert r == 0
+        assert np.abs(E - Etrue).max() <= 1e-13
+        assert np.abs(got[1:4]).max() <= 1e-12

@@ -56,6 +56,7 @@ class Setup:
     newton_maxit: int = 60
     xi: float = 0.0
     atm_factor: float = 1.001
+    frozen_matter: int = 0
     steps: int = 1
     # initial data (padded arrays, see module docstring)
     prim: Optional[np.ndarray] = None      # (5, Nz, Ny, Nx)
@@ -513,6 +514,33 @@ def random_states(shape3, seed=1, wmax=10.0, sigma_max=10.0, emax_frac=0.5, rho_
         s.E[d] = emax_frac * bmag * U(11 + d) / math.sqrt(3)
     s.face = face
     return s
+
+
+def steady_dynamo(n=128, k=1, eta=0.1, xi=0.5, rho=1e-14, p=1e-14, recon=MC, imex=SSP2, gamma=4.0 / 3.0):
+    """1-D steady mean-field dynamo (Sec 5.7): periodic x in [-pi, pi], fluid
+    at rest with the matter frozen, B^y = 0.1 sin(kx), B^z = -0.1 cos(kx),
+    E = 0, xi = 0.5.  eta = 0.1 is the reading under which the printed growth
+    rates hold (0.385 for k = 1, none for k = 5, 0.59 at the fastest k)."""
+    s = _blank(Setup("steady_dynamo", 1, (n, 1, 1), 3 if recon == PPM else 2, (-math.pi, 0, 0), (math.pi, 1, 1),
+                     _bc(1, PERIODIC), gamma, recon, imex, eta=eta, rho_atm=1e-3 * rho, p_atm=1e-3 * p, xi=xi,
+                     frozen_matter=1))
+    X, _, _ = s.mesh()
+    s.prim[0] = rho
+    s.prim[4] = p
+    face = np.zeros((3,) + s.shape)
+    face[1] = 0.1 * np.sin(k * X)
+    face[2] = -0.1 * np.cos(k * X)
+    s.face = face
+    return s
+
+
+def dynamo_growth_rate(k, eta=0.1, xi=0.5):
+    """growing root of g^2 + g/eta + k^2 - k xi/eta = 0: Maxwell's equations
+    with the Ohm's law J = (E - xi B)/eta of a fluid at rest, for the
+    force-free mode curl B = -k B of the initial field"""
+    b = 1.0 / eta
+    c = k * k - k * xi / eta
+    return 0.5 * (-b + math.sqrt(b * b - 4.0 * c))
 
 
 # ---------------------------------------------------------------------------
