@@ -247,6 +247,13 @@ def main():
     fails = run.fail_count()
     div = run.divB()
     extra = {"recovery_failures": int(fails), "divB_linf": float(div[2])}
+    # elliptic cleaning of the star's face fields after the timed steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    before, after = run.clean_divB(8)
+    extra["clean_divB"] = {"vcycles": 8, "ms": round((time.perf_counter() - t0) * 1e3, 3),
+                           "divB_L1_before": float(before[0]), "divB_L1_after": float(after[0]),
+                           "divB_linf_before": float(before[2]), "divB_linf_after": float(after[2])}
     roof = None
     if not args.no_extra:
         kname, roof, per_kernel = kernel_roofline(run, dt, args.steps, grmhd, torch)

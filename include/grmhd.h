@@ -138,6 +138,19 @@ gr_status gr_con2prim(const gr_grid *grid, gr_state *state, hipStream_t stream);
  * Uses the workspace scratch; deterministic reduction order. */
 gr_status gr_divB_norm(const gr_grid *grid, const gr_state *state, double *out3_dev, hipStream_t stream);
 
+/* Elliptic divergence cleaning of the face fields (Sec 3.3, eq. poisson and
+ * eq. update_bfield): solve L Phi = div q_B on the interior cells with
+ * `vcycles` multigrid V-cycles (red-black Gauss-Seidel 2+2, mean
+ * restriction, linear prolongation), then q_B^d -= dPhi/dx_d on every
+ * d-face of the interior, boundary faces included.  Outside a non-periodic
+ * boundary Phi is minus the boundary cell's value (Phi = 0 on the boundary
+ * face); periodic directions wrap.  Coarsening stops at the first level with
+ * an odd active size, which is then smoothed n^2 (<= 512) times per cycle, so
+ * grids whose sizes carry few factors of 2 converge slowly.  Scratch lives
+ * in the workspace.  out6_dev: NULL, or 6 device doubles receiving the
+ * (L1, L2, Linf) norms of div q_B before and after. */
+gr_status gr_clean_divB(const gr_grid *grid, gr_state *state, int vcycles, double *out6_dev, hipStream_t stream);
+
 /* Time step of Sec 2.5 (maximum-diffusivity speeds depend on the metric
  * only).  Synchronises the stream; result written to *dt_host. */
 gr_status gr_cfl_dt(const gr_grid *grid, const gr_state *state, double *dt_host, hipStream_t stream);

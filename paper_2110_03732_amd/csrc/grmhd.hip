@@ -28,6 +28,7 @@
 #include "common.h"
 #include "physics.h"
 #include "step_kernels.h"
+#include "mg_kernels.h"
 
 using namespace gr;
 
@@ -176,8 +177,50 @@ constexpr size_t kHeader = 1 << 20;  // failure counter + reduction partials
 constexpr int kMaxParts = 4096;
 
 struct Layout {
-    size_t sprim, sface, L, R, Lxy, EM, total_fields;
+    size_t sprim, sface, L, R, Lxy, EM, MG, total_fields;
 };
+
+// multigrid hierarchy of the divergence cleaning: level 0 is the interior,
+// each coarser level halves every active direction while all of them are
+// even and stay >= 2.  Returns the number of levels and the doubles needed
+// (three compact arrays per level); fills lv when given.
+constexpr int kMgMaxLevels = 24;
+int mg_levels(const gr_grid *g, MgLevel *lv, double *base, size_t *doubles)
+{
+    int n[3], act[3];
+    for (int d = 0; d < 3; d++) {
+        act[d] = d < g->ndim;
+        n[d] = act[d] ? g->n[d] : 1;
+    }
+    size_t tot = 0;
+    int nl = 0;
+    while (nl < kMgMaxLevels) {
+        size_t cells = (size_t)n[0] * n[1] * n[2];
+        if (lv) {
+            MgLevel &L = lv[nl];
+            for (int d = 0; d < 3; d++) {
+                L.n[d] = n[d];
+                L.act[d] = act[d];
+                L.per[d] = act[d] && g->bc[d][0] == GR_PERIODIC;
+                double h = act[d] ? (g->hi[d] - g->lo[d]) / g->n[d] * (double)(g->n[d] / n[d]) : 1.0;
+                L.ih2[d] = act[d] ? 1.0 / (h * h) : 0.0;
+            }
+            L.phi = base + tot;
+            L.rhs = base + tot + cells;
+            L.res = base + tot + 2 * cells;
+        }
+        tot += 3 * cells;
+        nl++;
+        bool more = true;
+        for (int d = 0; d < 3; d++)
+            if (act[d] && (n[d] % 2 != 0 || n[d] / 2 < 2)) more = false;
+        if (!more) break;
+        for (int d = 0; d < 3; d++)
+            if (act[d]) n[d] /= 2;
+    }
+    if (doubles) *doubles = tot;
+    return nl;
+}
 
 Layout layout(const gr_grid *g)
 {
@@ -196,6 +239,13 @@ Layout layout(const gr_grid *g)
     o += 8;
     L.EM = o;
     o += 3;
+    L.MG = o;
+    {
+        size_t mgd = 0;
+        mg_levels(g, nullptr, nullptr, &mgd);
+        Geo G = make_geo(g);
+        o += (mgd + (size_t)G.fs - 1) / (size_t)G.fs;
+    }
     L.total_fields = o;
     return L;
 }
@@ -1262,6 +1312,65 @@ gr_status gr_divB_norm(const gr_grid *g, const gr_state *st, double *out3, hipSt
     LAUNCHCHK();
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (int)nb, B.total, 0, part, out3);
     LAUNCHCHK();
+    return GR_OK;
+}
+
+gr_status gr_clean_divB(const gr_grid *g, gr_state *st, int vcycles, double *out6, hipStream_t s)
+{
+    gr_status v = gr_validate(g);
+    if (v != GR_OK) return v;
+    v = check_state(g, st);
+    if (v != GR_OK) return v;
+    if (vcycles < 0 || vcycles > 1000) return GR_EINVAL;
+    Geo G = make_geo(g);
+    Layout Ly = layout(g);
+    MgLevel lv[kMgMaxLevels];
+    const int nl = mg_levels(g, lv, wfield(st, G, Ly.MG), nullptr);
+    if (out6) {
+        v = gr_divB_norm(g, st, out6, s);
+        if (v != GR_OK) return v;
+    }
+    auto blocks = [](const MgLevel &L) {
+        long t = (long)L.n[0] * L.n[1] * L.n[2];
+        return dim3((unsigned)((t + 255) / 256));
+    };
+    hipLaunchKernelGGL(k_mg_div, blocks(lv[0]), dim3(256), 0, s, G, cptrs<3>(st->face, G.fs), lv[0]);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_mg_zero, blocks(lv[0]), dim3(256), 0, s, lv[0]);
+    LAUNCHCHK();
+    // coarsest level: Gauss-Seidel sweeps in proportion to its size
+    int nmax = 1;
+    for (int d = 0; d < 3; d++) nmax = lv[nl - 1].n[d] > nmax ? lv[nl - 1].n[d] : nmax;
+    const int coarse_sweeps = nmax * nmax > 512 ? 512 : (nmax * nmax < 4 ? 4 : nmax * nmax);
+    auto smooth = [&](const MgLevel &L, int sweeps) -> gr_status {
+        for (int i = 0; i < sweeps; i++)
+            for (int col = 0; col < 2; col++) {
+                hipLaunchKernelGGL(k_mg_smooth, blocks(L), dim3(256), 0, s, L, col);
+                LAUNCHCHK();
+            }
+        return GR_OK;
+    };
+    for (int cyc = 0; cyc < vcycles; cyc++) {
+        for (int l = 0; l < nl - 1; l++) {
+            if ((v = smooth(lv[l], 2)) != GR_OK) return v;
+            hipLaunchKernelGGL(k_mg_residual, blocks(lv[l]), dim3(256), 0, s, lv[l]);
+            LAUNCHCHK();
+            hipLaunchKernelGGL(k_mg_restrict, blocks(lv[l + 1]), dim3(256), 0, s, lv[l], lv[l + 1]);
+            LAUNCHCHK();
+        }
+        if ((v = smooth(lv[nl - 1], coarse_sweeps)) != GR_OK) return v;
+        for (int l = nl - 2; l >= 0; l--) {
+            hipLaunchKernelGGL(k_mg_prolong, blocks(lv[l]), dim3(256), 0, s, lv[l + 1], lv[l]);
+            LAUNCHCHK();
+            if ((v = smooth(lv[l], 2)) != GR_OK) return v;
+        }
+    }
+    Region R = region(G, 7);
+    dim3 gr, bl;
+    launch_dims(R, gr, bl);
+    hipLaunchKernelGGL(k_mg_apply, gr, bl, 0, s, G, lv[0], ptrs<3>(st->face, G.fs), R);
+    LAUNCHCHK();
+    if (out6) return gr_divB_norm(g, st, out6 + 3, s);
     return GR_OK;
 }
 

@@ -18,7 +18,7 @@ GR_OK, GR_EINVAL, GR_ENOMEM, GR_EHIP, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
 EXPORTED = ["gr_abi_version", "gr_strerror", "gr_validate", "gr_field_stride", "gr_workspace_bytes",
             "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim", "gr_divB_norm",
             "gr_cfl_dt", "gr_fail_count", "gr_timing_start", "gr_timing_read", "gr_kernel_class_name",
-            "gr_batch_create", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run", "gr_batch_stats", "gr_batch_tiles",
+            "gr_clean_divB", "gr_batch_create", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run", "gr_batch_stats", "gr_batch_tiles",
             "gr_tile_name", "gr_batch_destroy"]
 
 
@@ -69,6 +69,8 @@ def lib():
         L.gr_step.argtypes = [G, S, ctypes.c_double, V]
         L.gr_con2prim.argtypes = [G, S, V]
         L.gr_divB_norm.argtypes = [G, S, V, V]
+        L.gr_clean_divB.argtypes = [G, S, ctypes.c_int, V, V]
+        L.gr_clean_divB.restype = ctypes.c_int
         L.gr_cfl_dt.argtypes = [G, S, D, V]
         L.gr_fail_count.argtypes = [G, S, ctypes.POINTER(ctypes.c_ulonglong), V]
         L.gr_timing_start.argtypes = [ctypes.c_uint]
@@ -151,6 +153,11 @@ def gr_con2prim(grid, state, stream):
 def gr_divB_norm(grid, state, out3_dev_ptr, stream):
     _chk(lib().gr_divB_norm(ctypes.byref(grid), ctypes.byref(state), ctypes.c_void_p(out3_dev_ptr),
                             ctypes.c_void_p(stream)))
+
+
+def gr_clean_divB(grid, state, vcycles, out6_dev_ptr, stream):
+    _chk(lib().gr_clean_divB(ctypes.byref(grid), ctypes.byref(state), int(vcycles), ctypes.c_void_p(out6_dev_ptr),
+                             ctypes.c_void_p(stream)))
 
 
 def gr_cfl_dt(grid, state, stream):
@@ -312,6 +319,15 @@ class Run:
         gr_divB_norm(self.grid, self.state, out.data_ptr(), self.stream.cuda_stream)
         self.stream.synchronize()
         return out.cpu().numpy()
+
+    def clean_divB(self, vcycles=10):
+        """elliptic cleaning of the face fields; returns (L1, L2, Linf) of
+        div q_B before and after"""
+        out = self.torch.zeros(6, dtype=self.torch.float64, device=self.q.device)
+        gr_clean_divB(self.grid, self.state, vcycles, out.data_ptr(), self.stream.cuda_stream)
+        self.stream.synchronize()
+        o = out.cpu().numpy()
+        return o[:3], o[3:]
 
     def fail_count(self):
         return gr_fail_count(self.grid, self.state, self.stream.cuda_stream)
