@@ -283,3 +283,30 @@ def test_bitwise_deterministic():
         outs.append((run.prims(), run.faces(), run.cons()))
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name", ["tov_star_128_ppm_ssp3", "blast_512_ppm_ssp3_stiff", "shock_tube_400_10steps"])
+def test_full_size_parity(name):
+    """the benchmark workloads at their full sizes and launch configuration:
+    the 128^3 star and the 512^2 blast wave one step, the 400-cell shock tube
+    ten steps, element by element against the oracle"""
+    _torch()
+    say("full-size case %s" % name)
+    if name.startswith("tov"):
+        s, nsteps = W.tov_star(128), 1
+    elif name.startswith("blast"):
+        s, nsteps = W.blast_wave(512, eta=1e-6), 1
+    else:
+        s, nsteps = W.shock_tube(400), 10
+    run = gpu_run(s)
+    ref = oracle.OracleState(s)
+    dt = ref.dt()
+    for _ in range(nsteps):
+        run.step(dt)
+        ref.step(dt)
+    errs = compare_prims(s, run, ref, 1e-10)
+    compare_faces(s, run, ref, 1e-10)
+    compare_E(s, run, ref, 1e-10)
+    assert run.divB()[2] <= 1e-12
+    assert run.fail_count() == ref.nfail
+    say("  rel L1 %s" % ["%.1e" % e for e in errs])
