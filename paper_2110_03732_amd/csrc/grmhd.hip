@@ -347,6 +347,7 @@ const char *kCzName[CZ_COUNT] = {"16x16", "32x8"};
 
 struct Variant {
     int rec, met, xy, cz;
+    int xi;  // mean-field dynamo terms compiled into the cell pass
 };
 // tiles a run may use: two-dimensional x/y tiles when y is active, one-row
 // tiles otherwise (the metric 1-D case only the 256-wide one)
@@ -363,6 +364,7 @@ Variant default_variant(const gr_grid *g)
     V.met = g->metric ? 1 : 0;
     V.xy = g->ndim >= 2 ? XY_32x8 : XY_256x1;
     V.cz = CZ_16x16;
+    V.xi = g->xi != 0.0 ? 1 : 0;
     return V;
 }
 
@@ -477,11 +479,38 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
             GhostArgs &a = pl.gh;
             a.G = G;
             a.B = B;
-            a.R = region(G, 0, 7);
+            a.nslab = 0;
+            a.sb[0] = 0;
+            long shell = 0;
+            // slabs: z, then y inside the interior z, then x inside the interior y-z
+            for (int d = 2; d >= 0; d--) {
+                if (!G.act[d]) continue;
+                for (int side = 0; side < 2; side++) {
+                    Region R;
+                    for (int e = 0; e < 3; e++) {
+                        if (e > d) {  // already covered by the slabs of e: interior only
+                            R.lo[e] = G.g[e];
+                            R.cnt[e] = G.n[e];
+                        } else {
+                            R.lo[e] = 0;
+                            R.cnt[e] = G.N[e];
+                        }
+                    }
+                    R.lo[d] = side ? G.g[d] + G.n[d] : 0;
+                    R.cnt[d] = G.g[d];
+                    long pts = rtotal(R);
+                    if (pts == 0) continue;
+                    a.slab[a.nslab] = R;
+                    a.sb[a.nslab + 1] = a.sb[a.nslab] + (unsigned)((pts + kBlock - 1) / kBlock);
+                    a.nslab++;
+                    shell += pts;
+                }
+            }
             a.cells = ptrs<8>(sp_prev, G.fs);
             a.faces = ptrs<3>(sf_prev, G.fs);
-            a.gd = flat_dims(a.R);
-            pl.gh_bytes = 8.0 * (rtotal(a.R) - ncell) * 11 * 2;
+            a.gd.x = a.sb[a.nslab];
+            a.gd.y = a.gd.z = 1;
+            pl.gh_bytes = 8.0 * shell * 11 * 2;
         }
         // x/y phases: reads 8 stage fields, 3 face fields, the metric; writes 8
         pl.xy = true;
@@ -615,14 +644,19 @@ void launch_cell(const Variant &V, bool swz, const CellArgs &a, hipStream_t s)
 {
     with_rm(V.rec, V.met, [&](auto R, auto M) {
         constexpr int r = decltype(R)::value, m = decltype(M)::value;
-        if (!swz) {
-            hipLaunchKernelGGL((k_cell_update<r, m, 0, 1, 1>), d3(a.gd), dim3(kBlock), 0, s, a);
-            return;
-        }
-        with_cz(V.cz, [&](auto TX, auto TZ) {
-            hipLaunchKernelGGL((k_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value>), d3(a.gd),
-                               dim3(kBlock), 0, s, a);
-        });
+        auto go = [&](auto X) {
+            constexpr bool x = decltype(X)::value != 0;
+            if (!swz) {
+                hipLaunchKernelGGL((k_cell_update<r, m, 0, 1, 1, x>), d3(a.gd), dim3(kBlock), 0, s, a);
+                return;
+            }
+            with_cz(V.cz, [&](auto TX, auto TZ) {
+                hipLaunchKernelGGL((k_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value, x>), d3(a.gd),
+                                   dim3(kBlock), 0, s, a);
+            });
+        };
+        if (V.xi) go(IC<1>{});
+        else go(IC<0>{});
     });
 }
 
@@ -782,7 +816,7 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
                         }
                         BLaunch L;
                         L.cls = KC_SWEEP;
-                        L.V = Variant{rec, met, t, 0};
+                        L.V = Variant{rec, met, t, 0, 0};
                         add_group(stg, out, L, a, by);
                     }
         }
@@ -803,7 +837,7 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
                         BLaunch L;
                         L.cls = KC_CT;
                         L.K = kCtOrder[i];
-                        L.V = Variant{rec, met, 0, 0};
+                        L.V = Variant{rec, met, 0, 0, 0};
                         add_group(stg, out, L, a, by);
                     }
         }
@@ -824,24 +858,25 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
         if (cls_mask & (1u << KC_CELL_UPDATE)) {
             for (int rec = 0; rec < 3; rec++)
                 for (int met = 0; met < 2; met++)
-                    for (int sw = 0; sw < 2; sw++)
-                        for (int t = 0; t < (sw ? CZ_COUNT : 1); t++) {
-                            std::vector<const CellArgs *> a;
-                            std::vector<double> by;
-                            for (int r = 0; r < nr; r++) {
-                                const Variant &V = b->var[r];
-                                if (use[r] && V.rec == rec && V.met == met && (int)pl[r].swz == sw &&
-                                    (!sw || V.cz == t)) {
-                                    a.push_back(&pl[r].ca);
-                                    by.push_back(pl[r].ca_bytes);
+                    for (int xi = 0; xi < 2; xi++)
+                        for (int sw = 0; sw < 2; sw++)
+                            for (int t = 0; t < (sw ? CZ_COUNT : 1); t++) {
+                                std::vector<const CellArgs *> a;
+                                std::vector<double> by;
+                                for (int r = 0; r < nr; r++) {
+                                    const Variant &V = b->var[r];
+                                    if (use[r] && V.rec == rec && V.met == met && V.xi == xi &&
+                                        (int)pl[r].swz == sw && (!sw || V.cz == t)) {
+                                        a.push_back(&pl[r].ca);
+                                        by.push_back(pl[r].ca_bytes);
+                                    }
                                 }
+                                BLaunch L;
+                                L.cls = KC_CELL_UPDATE;
+                                L.V = Variant{rec, met, 0, t, xi};
+                                L.swz = sw;
+                                add_group(stg, out, L, a, by);
                             }
-                            BLaunch L;
-                            L.cls = KC_CELL_UPDATE;
-                            L.V = Variant{rec, met, 0, t};
-                            L.swz = sw;
-                            add_group(stg, out, L, a, by);
-                        }
         }
     }
     return GR_OK;
@@ -901,14 +936,19 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
         with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
             constexpr int r = decltype(R)::value, m = decltype(M)::value;
             const CellArgs *a = (const CellArgs *)L.args;
-            if (!L.swz) {
-                hipLaunchKernelGGL((kb_cell_update<r, m, 0, 1, 1>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
-                return;
-            }
-            with_cz(L.V.cz, [&](auto TX, auto TZ) {
-                hipLaunchKernelGGL((kb_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value>), grid,
-                                   dim3(kBlock), 0, s, a, L.start, L.n);
-            });
+            auto go = [&](auto X) {
+                constexpr bool x = decltype(X)::value != 0;
+                if (!L.swz) {
+                    hipLaunchKernelGGL((kb_cell_update<r, m, 0, 1, 1, x>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+                    return;
+                }
+                with_cz(L.V.cz, [&](auto TX, auto TZ) {
+                    hipLaunchKernelGGL((kb_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value, x>), grid,
+                                       dim3(kBlock), 0, s, a, L.start, L.n);
+                });
+            };
+            if (L.V.xi) go(IC<1>{});
+            else go(IC<0>{});
         });
         break;
     }
@@ -1291,8 +1331,8 @@ gr_status gr_con2prim(const gr_grid *g, gr_state *st, hipStream_t s)
     ca.A = A;
     ca.io = io;
     ca.gd = flat_dims(ca.R);
-    if (g->metric) hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 1, 0, 1, 1>), d3(ca.gd), dim3(kBlock), 0, s, ca);
-    else hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 0, 0, 1, 1>), d3(ca.gd), dim3(kBlock), 0, s, ca);
+    if (g->metric) hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 1, 0, 1, 1, false>), d3(ca.gd), dim3(kBlock), 0, s, ca);
+    else hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 0, 0, 1, 1, false>), d3(ca.gd), dim3(kBlock), 0, s, ca);
     LAUNCHCHK();
     return GR_OK;
 }

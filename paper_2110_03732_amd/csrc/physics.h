@@ -145,6 +145,9 @@ __device__ __forceinline__ void im_coef(double W, double et, double xi, ImCoef &
     c.Ad[5] = -x2 * et * iWpe2;
 }
 
+// XI: the mean-field dynamo terms are compiled in (xi != 0); the xi = 0
+// instance keeps the short form and its register budget
+template <bool XI>
 __device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], ImpEval &e)
 {
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -154,7 +157,7 @@ __device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], Imp
     e.iA0 = frcp(e.W + s.et);
     e.Esu = s.Es[0] * u[0] + s.Es[1] * u[1] + s.Es[2] * u[2];
     double uxB[3] = {u[1] * s.B[2] - u[2] * s.B[1], u[2] * s.B[0] - u[0] * s.B[2], u[0] * s.B[1] - u[1] * s.B[0]};
-    if (s.xi == 0.0) {
+    if (!XI) {
         double A1 = s.et * e.r1;
 #pragma unroll
         for (int i = 0; i < 3; i++) e.E[i] = (s.et * s.Es[i] + A1 * e.Esu * u[i] - uxB[i]) * e.iA0;
@@ -180,11 +183,12 @@ __device__ __forceinline__ void imp_eval(const ImpSys &s, const double u[3], Imp
     for (int i = 0; i < 3; i++) e.f[i] = e.wt * u[i] - (s.S[i] - ExB[i]);
 }
 
+template <bool XI>
 __device__ __forceinline__ void imp_jac(const ImpSys &s, const double u[3], const ImpEval &e, double J[3][3])
 {
     double iA0W = e.iA0 * e.iW;
     double dE[3][3];
-    if (s.xi == 0.0) {
+    if (!XI) {
         double A1 = s.et * e.r1, A1d = -s.et * s.et * e.r1 * e.r1;
 #pragma unroll
         for (int i = 0; i < 3; i++)
@@ -263,13 +267,14 @@ __device__ __forceinline__ bool solve3(const double J[3][3], const double b[3], 
 }
 
 // returns 0 converged, 1 not converged; u: guess in, root out
+template <bool XI>
 __device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int maxit, double u[3], ImpEval &e)
 {
     double J[3][3];
-    imp_eval(s, u, e);
+    imp_eval<XI>(s, u, e);
     double F = 0.5 * (e.f[0] * e.f[0] + e.f[1] * e.f[1] + e.f[2] * e.f[2]);
     for (int it = 0; it < maxit; it++) {
-        imp_jac(s, u, e, J);
+        imp_jac<XI>(s, u, e, J);
         double mf[3] = {-e.f[0], -e.f[1], -e.f[2]}, dx[3];
         if (!solve3(J, mf, dx)) return 1;
         double dmax = fmax(fabs(dx[0]), fmax(fabs(dx[1]), fabs(dx[2])));
@@ -278,7 +283,7 @@ __device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int m
             u[0] += dx[0];
             u[1] += dx[1];
             u[2] += dx[2];
-            imp_eval(s, u, e);
+            imp_eval<XI>(s, u, e);
             return 0;
         }
         double slope = -2.0 * F, lam = 1.0, un[3], Fn = 0.0;
@@ -288,7 +293,7 @@ __device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int m
             un[0] = u[0] + lam * dx[0];
             un[1] = u[1] + lam * dx[1];
             un[2] = u[2] + lam * dx[2];
-            imp_eval(s, un, en);
+            imp_eval<XI>(s, un, en);
             Fn = 0.5 * (en.f[0] * en.f[0] + en.f[1] * en.f[1] + en.f[2] * en.f[2]);
             if (isfinite(Fn) && Fn <= F + 1e-4 * lam * slope) {
                 ok = true;

@@ -56,10 +56,15 @@ __device__ __forceinline__ int map_face(const Geo &G, const BcArgs &B, int d, in
     return m;
 }
 
+// the ghost shell as up to six slabs (z low/high over the whole x-y extent,
+// y low/high inside the interior z range, x low/high inside the interior
+// y-z range); sb[i] is the first block of slab i, one thread per point
 struct GhostArgs {
     Geo G;
     BcArgs B;
-    Region R;
+    Region slab[6];
+    unsigned sb[7];
+    int nslab;
     Ptr<8> cells;
     Ptr<3> faces;
     GridDims gd;
@@ -70,8 +75,18 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &a, Blk blk)
     const BcArgs &B = a.B;
     const Ptr<8> &cells = a.cells;
     const Ptr<3> &faces = a.faces;
+    const unsigned L = blk.x;
+    int k = 0;
+    while (k + 1 < a.nslab && L >= a.sb[k + 1]) k++;
+    const Region &R = a.slab[k];
+    const long t = (long)(L - a.sb[k]) * blockDim.x + threadIdx.x;
+    const long cnt01 = (long)R.cnt[0] * R.cnt[1];
+    if (t >= cnt01 * R.cnt[2]) return;
     int c[3];
-    if (!region_point(a.R, blk, c)) return;
+    c[2] = R.lo[2] + (int)(t / cnt01);
+    const long r = t - (long)(c[2] - R.lo[2]) * cnt01;
+    c[1] = R.lo[1] + (int)(r / R.cnt[0]);
+    c[0] = R.lo[0] + (int)(r - (long)(c[1] - R.lo[1]) * R.cnt[0]);
     int s[3];
     bool move = false;
 #pragma unroll
@@ -371,7 +386,7 @@ template <int K>
 struct CtTile;
 template <>
 struct CtTile<2> {  // z-edges: a = x, b = y
-    static constexpr int T[3] = {32, 8, 1};
+    static constexpr int T[3] = {16, 16, 1};
 };
 template <>
 struct CtTile<1> {  // y-edges: a = z, b = x
@@ -379,7 +394,7 @@ struct CtTile<1> {  // y-edges: a = z, b = x
 };
 template <>
 struct CtTile<0> {  // x-edges: a = y, b = z
-    static constexpr int T[3] = {16, 4, 4};
+    static constexpr int T[3] = {16, 2, 8};
 };
 
 struct CtArgs {
@@ -617,7 +632,7 @@ struct CellArgs {
     CellIO io;
     GridDims gd;
 };
-template <int REC, int MET, int SWZ, int TX, int TZ>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI>
 __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
 {
     const Geo &G = args.G;
@@ -773,7 +788,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         const double Wf = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         sy.et = cell_eta(P, rho * Wf) / (al * A.aii_dt);
         ImpEval ev;
-        imp_eval(sy, u, ev);
+        imp_eval<XI>(sy, u, ev);
         stb(io.out[0], o, rho);
 #pragma unroll
         for (int i = 0; i < 3; i++) stb(io.out[1 + i], o, u[i] * ips2);
@@ -807,7 +822,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
             sy.et = eta / (al * A.aii_dt);
             sy.xi = P.xi;
             ImpEval ev;
-            int bad = implicit_solve(sy, P.tol, P.maxit, u, ev);
+            int bad = implicit_solve<XI>(sy, P.tol, P.maxit, u, ev);
             if (!bad) {
                 rho = D * ev.iW;
                 pr = (ev.wt * ev.iW - rho) * P.iG1;
@@ -884,18 +899,18 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     }
     if (status == 2) atomicAdd(io.nfail, 1ull);
 }
-template <int REC, int MET, int SWZ, int TX, int TZ>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI>
 __global__ void __launch_bounds__(kBlock) k_cell_update(CellArgs a)
 {
-    cell_body<REC, MET, SWZ, TX, TZ>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
+    cell_body<REC, MET, SWZ, TX, TZ, XI>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
 }
-template <int REC, int MET, int SWZ, int TX, int TZ>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI>
 __global__ void __launch_bounds__(kBlock)
     kb_cell_update(const CellArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
 {
     unsigned lb;
     const CellArgs &a = aa[batch_locate<SWZ != 0>(start, n, lb)];
-    cell_body<REC, MET, SWZ, TX, TZ>(a, blk_of(lb, a.gd));
+    cell_body<REC, MET, SWZ, TX, TZ, XI>(a, blk_of(lb, a.gd));
 }
 
 }  // namespace gr
