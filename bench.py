@@ -151,7 +151,8 @@ def batched_vs_plain(torch, W, grmhd, nruns, steps, seed=1):
     return out
 
 
-def served(torch, W, grmhd, nreq, rate, budgets_gib, seed=7):
+def served(torch, W, grmhd, nreq, rate, budgets_gib, seed=7, sweep_rates=(25.0, 50.0, 100.0, 200.0),
+           sweep_requests=48):
     """Poisson stream of 2-D blast waves (64^2..512^2) and 3-D stars
     (32^3..96^3), PPM + IMEX-SSP3, 10..500 steps, eta log-uniform; the
     requests' initial data is built before the clock starts (it arrives with
@@ -174,6 +175,15 @@ def served(torch, W, grmhd, nreq, rate, budgets_gib, seed=7):
         srv = serve.Server(int(gib * (1 << 30)), chunk=4)
         recs, summ = srv.serve(trace, payload)
         out["budget_%gGiB" % gib] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+    # arrival-rate sweep on the first requests of the same trace (32 GiB)
+    sweep = {}
+    for r in sweep_rates:
+        tr = W.served_trace(sweep_requests, rate=r, seed=seed)
+        srv = serve.Server(32 << 30, chunk=4)
+        _, summ = srv.serve(tr, payload)
+        sweep["%g" % r] = {k: round(summ[k], 4) for k in ("offered_zone_cycles_per_s", "served_zone_cycles_per_s",
+                                                          "p50_latency_s", "p99_latency_s", "makespan_s")}
+    out["rate_sweep_%d_requests" % sweep_requests] = sweep
     # plain path, requests back to back
     torch.cuda.synchronize()
     t0 = time.perf_counter()
