@@ -36,7 +36,8 @@ class OrGrid(ctypes.Structure):
                 ("sigma0", ctypes.c_double), ("eta_min", ctypes.c_double), ("eta_max", ctypes.c_double),
                 ("rho_atm", ctypes.c_double), ("p_atm", ctypes.c_double), ("metric", ctypes.c_int),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int), ("xi", ctypes.c_double),
-                ("atm_factor", ctypes.c_double), ("frozen_matter", ctypes.c_int)]
+                ("atm_factor", ctypes.c_double), ("frozen_matter", ctypes.c_int), ("glm", ctypes.c_int),
+                ("kappa_E", ctypes.c_double), ("kappa_B", ctypes.c_double)]
 
 
 _lib = None
@@ -74,6 +75,10 @@ def lib():
         L.or_cfl_dt.argtypes = [G, _D, _D]
         L.or_cfl_dt.restype = ctypes.c_double
         L.or_divB.argtypes = [G, _DD, _D]
+        L.or_step_glm.argtypes = [G, _DD, _DD, _DD, _D, _D, ctypes.c_double]
+        L.or_step_glm.restype = ctypes.c_long
+        L.or_explicit_L_glm.argtypes = [G, _DD, _D, _D, _DD]
+        L.or_divB_glm.argtypes = [G, _DD, _D]
         _lib = L
     return _lib
 
@@ -119,17 +124,21 @@ def grid_of(s) -> OrGrid:
     g.xi = s.xi
     g.atm_factor = s.atm_factor
     g.frozen_matter = s.frozen_matter
+    g.glm = s.glm
+    g.kappa_E = s.kappa_E
+    g.kappa_B = s.kappa_B
     return g
 
 
 class OracleState:
-    """q (8), face (3), prim (5) numpy arrays of padded cell shape"""
+    """q (8; 10 with GLM: + q_Psi, q_Phi), face (3: face-centred q_B, or
+    cell-centred q_B with GLM), prim (5) numpy arrays of padded cell shape"""
 
     def __init__(self, s):
         self.setup = s
         self.grid = grid_of(s)
         shp = s.shape
-        self.q = [np.zeros(shp) for _ in range(8)]
+        self.q = [np.zeros(shp) for _ in range(10 if s.glm else 8)]
         self.face = [np.zeros(shp) for _ in range(3)]
         self.prim = [np.zeros(shp) for _ in range(5)]
         self.alpha = np.ascontiguousarray(s.alpha) if s.metric else None
@@ -146,6 +155,8 @@ class OracleState:
                 self.face[d] += s.face[d]
             # conserved variables must see the added face field
             self._recons(prim_in, E_in)
+        if s.glm:
+            self.face = cell_centred_qB(s, self.face)
 
     def _recons(self, prim_in, E_in):
         s = self.setup
@@ -179,6 +190,12 @@ class OracleState:
             stage = [np.zeros(self.setup.shape) for _ in range(8)]
             if with_L:
                 L = [np.zeros(self.setup.shape) for _ in range(11)]
+        if self.setup.glm:
+            nf = lib().or_step_glm(ctypes.byref(self.grid), _pp(self.q), _pp(self.face), _pp(self.prim),
+                                   _p(self.alpha), _p(self.psi), dt)
+            self.nfail += nf
+            self.t += dt
+            return nf
         nf = lib().or_step(ctypes.byref(self.grid), _pp(self.q), _pp(self.face), _pp(self.prim), _p(self.alpha),
                            _p(self.psi), dt, max(dump_stage, 0), _pp(stage), _pp(L))
         self.nfail += nf
@@ -190,7 +207,10 @@ class OracleState:
 
     def divB(self):
         out = np.zeros(3)
-        lib().or_divB(ctypes.byref(self.grid), _pp(self.face), _p(out))
+        if self.setup.glm:
+            lib().or_divB_glm(ctypes.byref(self.grid), _pp(self.face), _p(out))
+        else:
+            lib().or_divB(ctypes.byref(self.grid), _pp(self.face), _p(out))
         return out
 
     def prims(self):
@@ -199,6 +219,22 @@ class OracleState:
     def E(self):
         ps6 = 1.0 if self.psi is None else self.psi ** 6
         return np.stack([self.q[5 + v] / ps6 for v in range(3)])
+
+
+def cell_centred_qB(s, face):
+    """GLM initial data: cell-centred q_B^d = mean of the two d-faces of the
+    cell (the face value along an inactive direction or at the array end)"""
+    out = []
+    for d in range(3):
+        f = face[d]
+        if not s.active(d):
+            out.append(f.copy())
+            continue
+        ax = 2 - d
+        up = np.concatenate([np.take(f, range(1, f.shape[ax]), axis=ax), np.take(f, [f.shape[ax] - 1], axis=ax)],
+                            axis=ax)
+        out.append(np.ascontiguousarray(0.5 * (f + up)))
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -52,6 +52,8 @@ typedef struct {
     double xi;           /* mean-field dynamo coefficient of eq. ohms_law     */
     double atm_factor;   /* cells with D <= atm_factor rho_atm are atmosphere */
     int frozen_matter;   /* 1: rho, u~, p stay fixed, only E and B evolve     */
+    int glm;             /* 1: cell-centred B with GLM cleaning (Sec 3.1)     */
+    double kappa_E, kappa_B; /* GLM damping parameters                        */
 } or_grid;
 
 enum { BC_OUTFLOW = 0, BC_PERIODIC = 1, BC_FIXED = 2 };
@@ -1473,6 +1475,343 @@ void or_divB(const or_grid *G, double **face, double out[3])
                 if (fabs(dv) > mx) mx = fabs(dv);
                 cnt++;
             }
+    out[0] = s1 / cnt;
+    out[1] = sqrt(s2 / cnt);
+    out[2] = mx;
+}
+
+
+/* ------------------------------------------------------------------------- */
+/* GLM hyperbolic divergence cleaning (Sec 3.1): the cell-centred alternative
+ * to constrained transport.  Conserved: q_D, q_S, q_tau, q_E (8), q_B^i (3,
+ * cell-centred, kept in the face[3] arrays at cell positions) and
+ * q_Psi = psi^6 Psi, q_Phi = psi^6 Phi (qc[8], qc[9]).  Fluxes: those of
+ * Sec 2.1, f_B of q_B^j along i = psi^6 eps^{jik} alpha E_k (Faraday),
+ * f_Psi^i = alpha q_E^i, f_Phi^i = alpha q_B^i (beta = 0).  Sources (K = 0):
+ * s_E^i += -alpha psi^6 gamma^{ij} d_j Psi, s_B^i = -alpha psi^6 gamma^{ij}
+ * d_j Phi, s_Psi = psi^6 [alpha rho_e - alpha kappa_E Psi + E^i d_i alpha],
+ * s_Phi = psi^6 [-alpha kappa_B Phi + B^i d_i alpha]; derivatives of Psi,
+ * Phi and alpha by central differences. */
+#define GLM_NV 13 /* reconstructed: rho, u~^i, p, E^i, B^i, Psi, Phi */
+
+typedef struct {
+    const or_grid *G;
+    geom q;
+    const double *v[GLM_NV]; /* cell arrays of the reconstructed variables */
+    const double *alpha, *psi;
+} gctx;
+
+static double gA(const gctx *c, long id) { return c->alpha ? c->alpha[id] : 1.0; }
+static double gP(const gctx *c, long id) { return c->psi ? c->psi[id] : 1.0; }
+
+static void glm_hll(const gctx *c, int d, const int cf[3], double F[GLM_NV])
+{
+    const geom *q = &c->q;
+    int cm[3] = {cf[0], cf[1], cf[2]};
+    cm[d] -= 1;
+    long i0 = IXv(q, cm), i1 = IXv(q, cf);
+    double al = 0.5 * (gA(c, i0) + gA(c, i1)), ps = 0.5 * (gP(c, i0) + gP(c, i1));
+    double sL[GLM_NV], sR[GLM_NV];
+    int kind = c->G->recon;
+    for (int v = 0; v < GLM_NV; v++) {
+        double w[6];
+        for (int m = 0; m < 6; m++) {
+            int cc[3] = {cf[0], cf[1], cf[2]};
+            cc[d] += m - 3;
+            w[m] = (kind != RC_PPM && (m == 0 || m == 5)) ? 0.0 : c->v[v][IXv(q, cc)];
+        }
+        or_recon(kind, w, &sL[v], &sR[v]);
+    }
+    double gam = c->G->gamma_ad, p6 = pow6(ps);
+    double qL[GLM_NV], qR[GLM_NV], fL[GLM_NV], fR[GLM_NV];
+    for (int side = 0; side < 2; side++) {
+        const double *st = side ? sR : sL;
+        double *qq = side ? qR : qL, *ff = side ? fR : fL;
+        const double *pr = st, *E = st + 5, *B = st + 8;
+        or_prim2cons(gam, ps, pr, E, B, qq);
+        or_flux(d, gam, al, ps, pr, E, B, ff);
+        or_flux_B(d, al, ps, E, ff + 8);
+        for (int j = 0; j < 3; j++) qq[8 + j] = p6 * B[j];
+        qq[11] = p6 * st[11];
+        qq[12] = p6 * st[12];
+        ff[11] = al * p6 * E[d];
+        ff[12] = al * p6 * B[d];
+    }
+    double sp = al * sqrt(1.0 / pow4(ps));
+    for (int v = 0; v < GLM_NV; v++) F[v] = (sp * fL[v] + sp * fR[v] - sp * sp * (qR[v] - qL[v])) / (sp + sp);
+}
+
+/* L of the GLM system on the interior cells (cell arrays include ghosts) */
+void or_explicit_L_glm(const or_grid *G, double **vars, const double *alpha, const double *psi, double **Lc)
+{
+    gctx c;
+    c.G = G;
+    c.q = mkgeom(G);
+    for (int v = 0; v < GLM_NV; v++) c.v[v] = vars[v];
+    c.alpha = G->metric ? alpha : NULL;
+    c.psi = G->metric ? psi : NULL;
+    geom *q = &c.q;
+    double *F[3][GLM_NV];
+    for (int d = 0; d < 3; d++) {
+        for (int v = 0; v < GLM_NV; v++) F[d][v] = NULL;
+        if (!q->act[d]) continue;
+        for (int v = 0; v < GLM_NV; v++) F[d][v] = (double *)calloc(q->ncell, sizeof(double));
+        int lo[3], hi[3];
+        for (int e = 0; e < 3; e++) {
+            lo[e] = q->g[e];
+            hi[e] = q->g[e] + q->n[e] + (e == d ? 1 : 0);
+        }
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int k = lo[2]; k < hi[2]; k++)
+            for (int j = lo[1]; j < hi[1]; j++)
+                for (int i = lo[0]; i < hi[0]; i++) {
+                    int cf[3] = {i, j, k};
+                    double Fv[GLM_NV];
+                    glm_hll(&c, d, cf, Fv);
+                    long id = IXv(q, cf);
+                    for (int v = 0; v < GLM_NV; v++) F[d][v][id] = Fv[v];
+                }
+    }
+    double gam = G->gamma_ad;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = q->g[2]; k < q->g[2] + q->n[2]; k++)
+        for (int j = q->g[1]; j < q->g[1] + q->n[1]; j++)
+            for (int i = q->g[0]; i < q->g[0] + q->n[0]; i++) {
+                int cc[3] = {i, j, k};
+                long id = IXv(q, cc);
+                double L[GLM_NV];
+                for (int v = 0; v < GLM_NV; v++) L[v] = 0.0;
+                for (int d = 0; d < 3; d++) {
+                    if (!q->act[d]) continue;
+                    int cp[3] = {i, j, k};
+                    cp[d] += 1;
+                    long ip = IXv(q, cp);
+                    for (int v = 0; v < GLM_NV; v++) L[v] -= (F[d][v][ip] - F[d][v][id]) / q->dx[d];
+                }
+                double al = gA(&c, id), ps = gP(&c, id);
+                metric3 m;
+                mk_metric(ps, &m);
+                double dal[3] = {0, 0, 0}, dps[3] = {0, 0, 0}, dPsi[3] = {0, 0, 0}, dPhi[3] = {0, 0, 0};
+                double divqE = 0.0;
+                for (int d = 0; d < 3; d++) {
+                    if (!q->act[d]) continue;
+                    int cp[3] = {i, j, k}, cm[3] = {i, j, k};
+                    cp[d] += 1;
+                    cm[d] -= 1;
+                    long ip = IXv(q, cp), im = IXv(q, cm);
+                    double h2 = 2.0 * q->dx[d];
+                    dal[d] = (gA(&c, ip) - gA(&c, im)) / h2;
+                    dps[d] = (gP(&c, ip) - gP(&c, im)) / h2;
+                    dPsi[d] = (vars[11][ip] - vars[11][im]) / h2;
+                    dPhi[d] = (vars[12][ip] - vars[12][im]) / h2;
+                    divqE += (pow6(gP(&c, ip)) * vars[5 + d][ip] - pow6(gP(&c, im)) * vars[5 + d][im]) / h2;
+                }
+                double pr[5], Ev[3], Bv[3];
+                for (int v = 0; v < 5; v++) pr[v] = vars[v][id];
+                for (int v = 0; v < 3; v++) {
+                    Ev[v] = vars[5 + v][id];
+                    Bv[v] = vars[8 + v][id];
+                }
+                double Psi = vars[11][id], Phi = vars[12][id];
+                double rho = pr[0], p = pr[4];
+                double ut[3] = {pr[1], pr[2], pr[3]};
+                double W = sqrt(1.0 + dotg(&m, ut, ut));
+                double v[3], vl[3], ExB[3], S[3], Su[3];
+                for (int a = 0; a < 3; a++) v[a] = ut[a] / W;
+                lower(&m, v, vl);
+                double eps = p / ((gam - 1.0) * rho), h = 1.0 + eps + p / rho;
+                double UEM = 0.5 * (dotg(&m, Ev, Ev) + dotg(&m, Bv, Bv));
+                cross_low(&m, Ev, Bv, ExB);
+                for (int a = 0; a < 3; a++) S[a] = rho * h * W * W * vl[a] + ExB[a];
+                raise_(&m, S, Su);
+                double tauD = rho * h * W * W - p + UEM;
+                if (G->metric) {
+                    double Sjk[3][3];
+                    for (int a = 0; a < 3; a++)
+                        for (int b = 0; b < 3; b++)
+                            Sjk[a][b] = rho * h * W * W * v[a] * v[b] + (p + UEM) * m.gi[a][b] - Ev[a] * Ev[b] -
+                                        Bv[a] * Bv[b];
+                    for (int a = 0; a < 3; a++) {
+                        double sg = 0.0;
+                        for (int jj = 0; jj < 3; jj++)
+                            for (int kk = 0; kk < 3; kk++) {
+                                double dg = (jj == kk) ? 4.0 * ps * ps * ps * dps[a] : 0.0;
+                                sg += 0.5 * al * Sjk[jj][kk] * dg;
+                            }
+                        L[1 + a] += m.sqrtg * (-tauD * dal[a] + sg);
+                    }
+                    double st = 0.0;
+                    for (int a = 0; a < 3; a++) st -= Su[a] * dal[a];
+                    L[4] += m.sqrtg * st;
+                }
+                double rhoe = divqE / m.sqrtg;
+                double Eda = 0.0, Bda = 0.0;
+                for (int a = 0; a < 3; a++) {
+                    L[5 + a] += -al * m.sqrtg * rhoe * v[a];
+                    double gPsi = 0.0, gPhi = 0.0; /* gamma^{ab} d_b */
+                    for (int b = 0; b < 3; b++) {
+                        gPsi += m.gi[a][b] * dPsi[b];
+                        gPhi += m.gi[a][b] * dPhi[b];
+                    }
+                    L[5 + a] += -al * m.sqrtg * gPsi;
+                    L[8 + a] += -al * m.sqrtg * gPhi;
+                    Eda += Ev[a] * dal[a];
+                    Bda += Bv[a] * dal[a];
+                }
+                L[11] += m.sqrtg * (al * rhoe - al * G->kappa_E * Psi + Eda);
+                L[12] += m.sqrtg * (-al * G->kappa_B * Phi + Bda);
+                for (int vv = 0; vv < GLM_NV; vv++) Lc[vv][id] = L[vv];
+            }
+    for (int d = 0; d < 3; d++)
+        for (int v = 0; v < GLM_NV; v++) free(F[d][v]);
+}
+
+/* One IMEX step of the GLM system; the conserved set is q (10: D, S, tau,
+ * E, Psi, Phi) and qB (3, cell-centred).  Same tableau use as or_step;
+ * B, Psi and Phi are explicit (R = 0 for them). */
+long or_step_glm(const or_grid *G, double **qc, double **qB, double **prim, const double *alpha, const double *psi,
+                 double dt)
+{
+    geom q = mkgeom(G);
+    const double *al_arr = G->metric ? alpha : NULL;
+    const double *ps_arr = G->metric ? psi : NULL;
+    double At[16], A[16], wt[4], w[4];
+    int s = or_tableau(G->imex, At, A, wt, w);
+    long nc = q.ncell, nfail = 0;
+    /* stage variables (undensitised): prims 5, E 3, B 3, Psi, Phi */
+    double *sv[4][GLM_NV], *Lc[4][GLM_NV], *R[4][3];
+    int Lhave[4] = {0, 0, 0, 0};
+    for (int i = 0; i < s; i++) {
+        for (int v = 0; v < GLM_NV; v++) {
+            sv[i][v] = (double *)malloc(nc * sizeof(double));
+            Lc[i][v] = (double *)calloc(nc, sizeof(double));
+        }
+        for (int v = 0; v < 3; v++) R[i][v] = (double *)calloc(nc, sizeof(double));
+        for (long id = 0; id < nc; id++) {
+            double p6 = pow6(ps_arr ? ps_arr[id] : 1.0);
+            for (int v = 0; v < 5; v++) sv[i][v][id] = prim[v][id];
+            for (int v = 0; v < 3; v++) {
+                sv[i][5 + v][id] = qc[5 + v][id] / p6;
+                sv[i][8 + v][id] = qB[v][id] / p6;
+            }
+            sv[i][11][id] = qc[8][id] / p6;
+            sv[i][12][id] = qc[9][id] / p6;
+        }
+    }
+    /* conserved-variable index of L component v: L[0..7] -> q[0..7],
+     * L[8..10] -> qB, L[11] -> q[8], L[12] -> q[9] */
+    for (int i = 0; i < s; i++) {
+        for (int j = 0; j < i; j++) {
+            if (At[i * 4 + j] != 0.0 && !Lhave[j]) {
+                or_ghost_fill(G, sv[j], GLM_NV, NULL);
+                or_explicit_L_glm(G, sv[j], al_arr, ps_arr, Lc[j]);
+                Lhave[j] = 1;
+            }
+        }
+        double aii = A[i * 4 + i];
+        for (int k = q.g[2]; k < q.g[2] + q.n[2]; k++)
+            for (int jj = q.g[1]; jj < q.g[1] + q.n[1]; jj++)
+                for (int ii = q.g[0]; ii < q.g[0] + q.n[0]; ii++) {
+                    long id = IX(&q, ii, jj, k);
+                    double qs[GLM_NV];
+                    for (int v = 0; v < GLM_NV; v++) {
+                        double acc = v < 8 ? qc[v][id] : (v < 11 ? qB[v - 8][id] : qc[v - 3][id]);
+                        for (int j = 0; j < i; j++) {
+                            acc += dt * At[i * 4 + j] * Lc[j][v][id];
+                            if (v >= 5 && v < 8) acc += dt * A[i * 4 + j] * R[j][v - 5][id];
+                        }
+                        qs[v] = acc;
+                    }
+                    double ps = ps_arr ? ps_arr[id] : 1.0, al = al_arr ? al_arr[id] : 1.0, p6 = pow6(ps);
+                    double B[3] = {qs[8] / p6, qs[9] / p6, qs[10] / p6};
+                    double guess[3], pr[5], E[3], fz[5];
+                    double **gp = (i == 0) ? prim : sv[i - 1];
+                    for (int a = 0; a < 3; a++) guess[a] = gp[1 + a][id];
+                    if (G->frozen_matter)
+                        for (int v = 0; v < 5; v++) fz[v] = prim[v][id];
+                    int r = cell_implicit(G, al, ps, qs, B, aii, dt, guess, G->frozen_matter ? fz : NULL, pr, E);
+                    if (r == 2) nfail++;
+                    for (int v = 0; v < 5; v++) sv[i][v][id] = pr[v];
+                    for (int a = 0; a < 3; a++) {
+                        sv[i][5 + a][id] = E[a];
+                        sv[i][8 + a][id] = B[a];
+                        R[i][a][id] = (p6 * E[a] - qs[5 + a]) / (aii * dt);
+                    }
+                    sv[i][11][id] = qs[11] / p6;
+                    sv[i][12][id] = qs[12] / p6;
+                }
+    }
+    for (int j = 0; j < s; j++) {
+        if (wt[j] != 0.0 && !Lhave[j]) {
+            or_ghost_fill(G, sv[j], GLM_NV, NULL);
+            or_explicit_L_glm(G, sv[j], al_arr, ps_arr, Lc[j]);
+            Lhave[j] = 1;
+        }
+    }
+    for (int k = q.g[2]; k < q.g[2] + q.n[2]; k++)
+        for (int jj = q.g[1]; jj < q.g[1] + q.n[1]; jj++)
+            for (int ii = q.g[0]; ii < q.g[0] + q.n[0]; ii++) {
+                long id = IX(&q, ii, jj, k);
+                for (int v = G->frozen_matter ? 5 : 0; v < GLM_NV; v++) {
+                    double *dst = v < 8 ? &qc[v][id] : (v < 11 ? &qB[v - 8][id] : &qc[v - 3][id]);
+                    double acc = *dst;
+                    for (int j = 0; j < s; j++) {
+                        acc += dt * wt[j] * Lc[j][v][id];
+                        if (v >= 5 && v < 8) acc += dt * w[j] * R[j][v - 5][id];
+                    }
+                    *dst = acc;
+                }
+                if (G->frozen_matter) continue;
+                double ps = ps_arr ? ps_arr[id] : 1.0, p6 = pow6(ps);
+                double B[3] = {qB[0][id] / p6, qB[1][id] / p6, qB[2][id] / p6};
+                double qq[8], pr[5];
+                for (int v = 0; v < 8; v++) qq[v] = qc[v][id];
+                int r = cell_c2p(G, ps, qq, B, pr);
+                if (r == 2) nfail++;
+                for (int v = 0; v < 8; v++) qc[v][id] = qq[v];
+                for (int v = 0; v < 5; v++) prim[v][id] = pr[v];
+            }
+    for (int i = 0; i < s; i++) {
+        for (int v = 0; v < GLM_NV; v++) {
+            free(sv[i][v]);
+            free(Lc[i][v]);
+        }
+        for (int v = 0; v < 3; v++) free(R[i][v]);
+    }
+    return nfail;
+}
+
+/* cell-centred divergence of the GLM q_B: central differences over the
+ * interior cells, with the boundary rule supplying the outer neighbours
+ * (L1 = mean |div|, L2, Linf) */
+void or_divB_glm(const or_grid *G, double **qB, double out[3])
+{
+    geom q = mkgeom(G);
+    double *tmp[3];
+    for (int d = 0; d < 3; d++) {
+        tmp[d] = (double *)malloc(q.ncell * sizeof(double));
+        memcpy(tmp[d], qB[d], q.ncell * sizeof(double));
+    }
+    or_ghost_fill(G, tmp, 3, NULL);
+    double s1 = 0.0, s2 = 0.0, mx = 0.0;
+    long cnt = 0;
+    for (int k = q.g[2]; k < q.g[2] + q.n[2]; k++)
+        for (int j = q.g[1]; j < q.g[1] + q.n[1]; j++)
+            for (int i = q.g[0]; i < q.g[0] + q.n[0]; i++) {
+                double dv = 0.0;
+                for (int d = 0; d < 3; d++) {
+                    if (!q.act[d]) continue;
+                    int cp[3] = {i, j, k}, cm[3] = {i, j, k};
+                    cp[d] += 1;
+                    cm[d] -= 1;
+                    dv += (tmp[d][IXv(&q, cp)] - tmp[d][IXv(&q, cm)]) / (2.0 * q.dx[d]);
+                }
+                s1 += fabs(dv);
+                s2 += dv * dv;
+                if (fabs(dv) > mx) mx = fabs(dv);
+                cnt++;
+            }
+    for (int d = 0; d < 3; d++) free(tmp[d]);
     out[0] = s1 / cnt;
     out[1] = sqrt(s2 / cnt);
     out[2] = mx;

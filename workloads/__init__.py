@@ -57,6 +57,9 @@ class Setup:
     xi: float = 0.0
     atm_factor: float = 1.001
     frozen_matter: int = 0
+    glm: int = 0               # 1: cell-centred B with GLM cleaning (Sec 3.1)
+    kappa_E: float = 1.0
+    kappa_B: float = 1.0
     steps: int = 1
     # initial data (padded arrays, see module docstring)
     prim: Optional[np.ndarray] = None      # (5, Nz, Ny, Nx)
@@ -530,6 +533,47 @@ def steady_dynamo(n=128, k=1, eta=0.1, xi=0.5, rho=1e-14, p=1e-14, recon=MC, ime
     face = np.zeros((3,) + s.shape)
     face[1] = 0.1 * np.sin(k * X)
     face[2] = -0.1 * np.cos(k * X)
+    s.face = face
+    return s
+
+
+def glm_wave(n=128, k=1, kappa=1.0, b=1e-3, rho=1.0, p=1.0, recon=MC, imex=SSP2):
+    """1-D periodic x in [-pi, pi], fluid at rest and frozen, B^x = b sin(kx)
+    (a pure divergence), E = 0, GLM with kappa_B = kappa_E = kappa.  The
+    (B^x, Phi) pair obeys B'' + kappa B' + k^2 B = 0 (Sec 3.1 with v = 0)."""
+    s = _blank(Setup("glm_wave", 1, (n, 1, 1), 3 if recon == PPM else 2, (-math.pi, 0, 0), (math.pi, 1, 1),
+                     _bc(1, PERIODIC), 5.0 / 3.0, recon, imex, eta=1e-3, rho_atm=1e-6 * rho, p_atm=1e-6 * p,
+                     frozen_matter=1, glm=1, kappa_E=kappa, kappa_B=kappa))
+    X, _, _ = s.mesh()
+    s.prim[0] = rho
+    s.prim[4] = p
+    face = np.zeros((3,) + s.shape)
+    # the cell-centred field is the mean of the two faces: these face values
+    # make it exactly b sin(k x_cell)
+    dx = s.dx(0)
+    face[0] = b * np.sin(k * (X - 0.5 * dx)) / math.cos(0.5 * k * dx)
+    s.face = face
+    return s
+
+
+def glm_monopole(n=64, kappa=1.0, R=0.2, ndim=3, ext=2.0, recon=MC, imex=SSP2):
+    """Gaussian magnetic monopole (Sec 5.8): B^x = exp(-r^2/R^2) - exp(-1) for
+    r < R, uniform rho = 1, eps = 0.1 (p = (Gamma - 1) rho eps), v = 0,
+    Gamma = 5/3, eta = 1e-16, GLM with kappa_E = kappa_B = kappa, domain
+    [-ext, ext]^ndim, outflow."""
+    nn = (n, n if ndim > 1 else 1, n if ndim > 2 else 1)
+    lo = tuple(-ext if d < ndim else 0.0 for d in range(3))
+    hi = tuple(ext if d < ndim else 1.0 for d in range(3))
+    s = _blank(Setup("glm_monopole", ndim, nn, 3 if recon == PPM else 2, lo, hi, _bc(ndim, OUTFLOW), 5.0 / 3.0,
+                     recon, imex, eta=1e-16, rho_atm=1e-8, p_atm=1e-10, glm=1, kappa_E=kappa, kappa_B=kappa))
+    s.prim[0] = 1.0
+    s.prim[4] = (5.0 / 3.0 - 1.0) * 0.1
+    # faces: B^x at the x-faces from the profile at face positions
+    X, Y, Z = s.mesh()
+    Xf = (X - 0.5 * s.dx(0), Y, Z)
+    r2 = sum(a ** 2 for a in Xf[:ndim])
+    face = np.zeros((3,) + s.shape)
+    face[0] = np.where(r2 < R * R, np.exp(-r2 / (R * R)) - math.exp(-1.0), 0.0)
     s.face = face
     return s
 
