@@ -17,7 +17,10 @@
  *   - q: 8 fields, the densitised conserved variables of Sec 2.1,
  *     (q_D, q_S_x, q_S_y, q_S_z, q_tau, q_E^x, q_E^y, q_E^z), q = psi^6 (...);
  *   - face: 3 fields, face-centred q_B^d = psi^6 B^d (Sec 3.2); field d at
- *     index (i,j,k) sits half a cell below the cell centre in direction d;
+ *     index (i,j,k) sits half a cell below the cell centre in direction d.
+ *     With glm = 1 (Sec 3.1) the same 3 fields hold the cell-centred q_B^d
+ *     and q holds 10 fields: the 8 above, then q_Psi = psi^6 Psi and
+ *     q_Phi = psi^6 Phi;
  *   - prim: 5 fields (rho, u~^x, u~^y, u~^z, p), u~^i = W v^i (Sec 2.4);
  *   - metric: NULL (flat) or 2 fields (lapse alpha, conformal factor psi) of
  *     a static conformally flat metric, gamma_ij = psi^4 delta_ij, beta = 0.
@@ -39,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 2
+#define GR_ABI_VERSION 3
 
 typedef enum {
     GR_OK = 0,
@@ -74,6 +77,8 @@ typedef struct gr_grid {
     double xi;            /* mean-field dynamo coefficient of eq. ohms_law      */
     double atm_factor;    /* cells with D <= atm_factor rho_atm are atmosphere  */
     int frozen_matter;    /* 1: rho, u~, p stay fixed and only E and B evolve   */
+    int glm;              /* 1: cell-centred B with GLM cleaning (Sec 3.1)      */
+    double kappa_E, kappa_B; /* GLM damping parameters                          */
 } gr_grid;
 
 /* Device state of one run (all pointers caller-owned device memory). */
@@ -100,9 +105,11 @@ size_t gr_field_stride(const gr_grid *grid);
 size_t gr_workspace_bytes(const gr_grid *grid);
 
 /* Byte offset inside the workspace of one field of stage storage, for
- * inspection: kind 0 = stage primitives + E (8 fields: rho, u~, p, E^i),
- * 1 = stage face fields (3), 2 = stored L (11: 8 cell + 3 face), 3 = stored
- * R (3, q_E rows).  stage is 0-based (< number of implicit stages). */
+ * inspection: kind 0 = stage primitives + E (8 fields: rho, u~, p, E^i;
+ * with glm 10: + Psi, Phi), 1 = stage face fields (3; with glm the cell q_B),
+ * 2 = stored L (11: 8 cell + 3 face; with glm 13: 8 cell, q_B, q_Psi,
+ * q_Phi), 3 = stored R (3, q_E rows).  stage is 0-based (< number of
+ * implicit stages); a field index beyond the kind's count is GR_EINVAL. */
 gr_status gr_workspace_offset(const gr_grid *grid, int kind, int stage, int field, size_t *offset_bytes);
 
 /* Initial state (Sec 4 and Sec 2.1): face fields q_B^i = eta^{ijk} d_j A_k
@@ -112,7 +119,11 @@ gr_status gr_workspace_offset(const gr_grid *grid, int kind, int stage, int fiel
  * prim_host: 5 cell arrays, E_host: 3 cell arrays, metric_host: 2 cell arrays
  * (alpha, psi) or NULL; all with the cell-array layout above (contiguous,
  * stride Nx Ny Nz between fields).  Also resets the failure counter and fills
- * the ghost points of the workspace stage storage.  Synchronises the stream. */
+ * the ghost points of the workspace stage storage.  With glm the face
+ * fields are then turned into the cell-centred q_B^d (mean of the cell's two
+ * d-faces; the face value itself along an inactive direction and at the last
+ * point of the array) and q_Psi = q_Phi = 0 (Sec 3.1).  Synchronises the
+ * stream. */
 gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim_host, const double *E_host,
                         const double *A_host, const double *face_host, const double *metric_host,
                         hipStream_t stream);
@@ -129,12 +140,15 @@ gr_status gr_imex_stage(const gr_grid *grid, gr_state *state, int pass, double d
 gr_status gr_step(const gr_grid *grid, gr_state *state, double dt, hipStream_t stream);
 
 /* Primitive recovery with E and B known (Sec 2.6) on the interior cells of
- * the state; atmosphere and failure rules as in the step. */
+ * the state; atmosphere and failure rules as in the step.  B is the cell
+ * mean of the face fields, or the cell q_B with glm. */
 gr_status gr_con2prim(const gr_grid *grid, gr_state *state, hipStream_t stream);
 
 /* Discrete divergence of the face field on interior cells,
  * div = sum_d (q_B^d(+1/2) - q_B^d(-1/2)) / dx_d (Sec 3, eq. divb_0):
  * out3_dev[0] = mean |div|, [1] = sqrt(mean div^2), [2] = max |div|.
+ * With glm: central differences of the cell q_B, sum_d (q_B^d(+1) -
+ * q_B^d(-1)) / (2 dx_d), the boundary rule giving the outside neighbour.
  * Uses the workspace scratch; deterministic reduction order. */
 gr_status gr_divB_norm(const gr_grid *grid, const gr_state *state, double *out3_dev, hipStream_t stream);
 
@@ -148,7 +162,8 @@ gr_status gr_divB_norm(const gr_grid *grid, const gr_state *state, double *out3_
  * an odd active size, which is then smoothed n^2 (<= 512) times per cycle, so
  * grids whose sizes carry few factors of 2 converge slowly.  Scratch lives
  * in the workspace.  out6_dev: NULL, or 6 device doubles receiving the
- * (L1, L2, Linf) norms of div q_B before and after. */
+ * (L1, L2, Linf) norms of div q_B before and after.  A GLM grid (cell-centred
+ * q_B) returns GR_EUNSUPPORTED. */
 gr_status gr_clean_divB(const gr_grid *grid, gr_state *state, int vcycles, double *out6_dev, hipStream_t stream);
 
 /* Time step of Sec 2.5 (maximum-diffusivity speeds depend on the metric

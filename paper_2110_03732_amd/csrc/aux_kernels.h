@@ -116,6 +116,26 @@ __global__ void __launch_bounds__(256) k_stage_copy(Geo G, int met_on, CPtr<5> p
     for (int i = 0; i < 3; i++) sp.p[5 + i][t] = q.p[5 + i][t] * ips6;
 }
 
+// GLM initial data (Sec 3.1): cell-centred q_B^d = mean of the cell's two
+// d-faces (the face value itself along an inactive direction and at the last
+// point of the padded array); every padded point
+__global__ void __launch_bounds__(256) k_face_to_cell(Geo G, CPtr<3> face, Ptr<3> cell)
+{
+    int c[3];
+    int tt = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tt >= G.N[0] * G.N[1]) return;
+    c[1] = tt / G.N[0];
+    c[0] = tt - c[1] * G.N[0];
+    c[2] = blockIdx.y;
+    int t = lin(G, c);
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        double f = face.p[d][t];
+        if (G.act[d] && c[d] + 1 < G.N[d]) f = 0.5 * (f + face.p[d][t + G.st[d]]);
+        cell.p[d][t] = f;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // reductions: per-block partials (sum |x|, sum x^2, max |x|), then one block;
 // fixed tree order, so the result does not depend on scheduling
@@ -152,6 +172,37 @@ __global__ void __launch_bounds__(256) k_divb_partial(Geo G, FlatBox R, CPtr<3> 
 #pragma unroll
         for (int d = 0; d < 3; d++)
             if (G.act[d]) dv += (face.p[d][id + G.st[d]] - face.p[d][id]) * G.idx[d];
+        a += fabs(dv);
+        b += dv * dv;
+        c = fmax(c, fabs(dv));
+    }
+    block_reduce3(a, b, c);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = a;
+        part[3 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// GLM: central-difference divergence of the cell-centred q_B over the
+// interior, the boundary rule supplying the neighbour outside
+__global__ void __launch_bounds__(256) k_divb_cc_partial(Geo G, FlatBox R, BcArgs Bc, CPtr<3> qB,
+                                                         double *__restrict__ part)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < R.total; t += (long)gridDim.x * blockDim.x) {
+        int id = flat_point(G, R, t);
+        int p[3];
+        p[2] = id / G.st[2];
+        p[1] = (id - p[2] * G.st[2]) / G.st[1];
+        p[0] = id - p[2] * G.st[2] - p[1] * G.st[1];
+        double dv = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            if (!G.act[d]) continue;
+            int up = map_cell(G, Bc, d, p[d] + 1), dn = map_cell(G, Bc, d, p[d] - 1);
+            dv += (qB.p[d][id + (up - p[d]) * G.st[d]] - qB.p[d][id + (dn - p[d]) * G.st[d]]) * (0.5 * G.idx[d]);
+        }
         a += fabs(dv);
         b += dv * dv;
         c = fmax(c, fabs(dv));

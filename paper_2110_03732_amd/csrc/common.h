@@ -217,4 +217,41 @@ __device__ __forceinline__ void recon_at(const double *__restrict__ a, int id, i
     recon_face<REC>(w, L, R);
 }
 
+// ---------------------------------------------------------------------------
+// boundary rules as index maps: the point whose value a ghost point takes
+// (outflow: the nearest interior point; periodic: the image; fixed: itself)
+struct BcArgs {
+    int bc[3][2];
+};
+
+__device__ __forceinline__ int map_cell(const Geo &G, const BcArgs &B, int d, int m)
+{
+    if (!G.act[d]) return m;
+    int g = G.g[d], n = G.n[d];
+    if (m < g) {
+        int b = B.bc[d][0];
+        return b == GR_OUTFLOW ? g : (b == GR_PERIODIC ? m + n : m);
+    }
+    if (m >= g + n) {
+        int b = B.bc[d][1];
+        return b == GR_OUTFLOW ? g + n - 1 : (b == GR_PERIODIC ? m - n : m);
+    }
+    return m;
+}
+// normal face field of direction d: faces g .. g+n are evolved
+__device__ __forceinline__ int map_face(const Geo &G, const BcArgs &B, int d, int m)
+{
+    if (!G.act[d]) return m;
+    int g = G.g[d], n = G.n[d];
+    if (m < g) {
+        int b = B.bc[d][0];
+        return b == GR_OUTFLOW ? g : (b == GR_PERIODIC ? m + n : m);
+    }
+    if (m > g + n) {
+        int b = B.bc[d][1];
+        return b == GR_OUTFLOW ? g + n : (b == GR_PERIODIC ? m - n : m);
+    }
+    return m;
+}
+
 }  // namespace gr

@@ -106,6 +106,8 @@ Phys make_phys(const gr_grid *g)
     P.maxit = g->newton_maxit;
     P.xi = g->xi;
     P.frozen = g->frozen_matter;
+    P.kappa_E = g->kappa_E;
+    P.kappa_B = g->kappa_B;
     P.eta_mode = g->eta_mode;
     P.eta = g->eta;
     P.sigma0 = g->sigma0;
@@ -178,6 +180,7 @@ constexpr int kMaxParts = 4096;
 
 struct Layout {
     size_t sprim, sface, L, R, Lxy, EM, MG, total_fields;
+    int nsp, nL, nLxy;  // fields per stage block / stored L / x-y divergence
 };
 
 // multigrid hierarchy of the divergence cleaning: level 0 is the interior,
@@ -226,17 +229,22 @@ Layout layout(const gr_grid *g)
 {
     Tableau T = tableau(g->imex);
     Layout L;
+    // GLM: stage blocks also hold Psi, Phi; stored L and the x-y divergence
+    // carry q_B (cell centred), q_Psi and q_Phi
+    L.nsp = g->glm ? 10 : 8;
+    L.nL = g->glm ? 13 : 11;
+    L.nLxy = g->glm ? 13 : 8;
     size_t o = 0;
     L.sprim = o;
-    o += 8 * (size_t)T.s;
+    o += (size_t)L.nsp * T.s;
     L.sface = o;
     o += 3 * (size_t)T.s;
     L.L = o;
-    o += 11 * (size_t)T.s;
+    o += (size_t)L.nL * T.s;
     L.R = o;
     o += 3 * (size_t)T.s;
     L.Lxy = o;
-    o += 8;
+    o += (size_t)L.nLxy;
     L.EM = o;
     o += 3;
     L.MG = o;
@@ -347,12 +355,14 @@ const char *kCzName[CZ_COUNT] = {"16x16", "32x8"};
 
 struct Variant {
     int rec, met, xy, cz;
-    int xi;  // mean-field dynamo terms compiled into the cell pass
+    int xi;   // mean-field dynamo terms compiled into the cell pass
+    int glm;  // GLM cleaning (cell-centred B): default tiles only
 };
 // tiles a run may use: two-dimensional x/y tiles when y is active, one-row
 // tiles otherwise (the metric 1-D case only the 256-wide one)
 bool xy_allowed(const gr_grid *g, int t)
 {
+    if (g->glm) return t == (g->ndim >= 2 ? XY_32x8 : XY_256x1);
     if (g->ndim >= 2) return t <= XY_16x16;
     if (g->metric) return t == XY_256x1;
     return t >= XY_256x1;
@@ -365,6 +375,7 @@ Variant default_variant(const gr_grid *g)
     V.xy = g->ndim >= 2 ? XY_32x8 : XY_256x1;
     V.cz = CZ_16x16;
     V.xi = g->xi != 0.0 ? 1 : 0;
+    V.glm = g->glm ? 1 : 0;
     return V;
 }
 
@@ -400,10 +411,17 @@ void with_cz(int t, F &&f)
     else f(IC<16>{}, IC<16>{});
 }
 // instances that no allowed variant selects are not compiled
-template <int MET, int TX, int TY>
+template <int MET, int TX, int TY, bool GLM = false>
 constexpr bool xy_compiled()
 {
+    if (GLM) return (TX == 32 && TY == 8) || (TX == 256 && TY == 1);
     return !(MET == 1 && TY == 1 && TX != 256);
+}
+template <class F>
+void with_glm(int glm, F &&f)
+{
+    if (glm) f(IC<1>{});
+    else f(IC<0>{});
 }
 
 const int kCtOrder[3] = {2, 0, 1};
@@ -455,11 +473,13 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
         A.cL[j] = fin ? T.wt[j] : T.At[p][j];
         A.cR[j] = fin ? T.w[j] : T.A[p][j];
     }
-    // face block of stage j: the state's own faces while no explicit term has entered
+    const bool glm = g->glm != 0;
+    // face block of stage j: the state's own faces while no explicit term has
+    // entered (CT); GLM keeps a stage q_B block per stage, written by the cell pass
     auto stage_face = [&](int j) -> double * {
-        return faces_are_n(T, j) ? st->face : wfield(st, G, Ly.sface + 3 * (size_t)j);
+        return (faces_are_n(T, j) && !glm) ? st->face : wfield(st, G, Ly.sface + 3 * (size_t)j);
     };
-    double *sp_prev = (p >= 1) ? wfield(st, G, Ly.sprim + 8 * (size_t)(p - 1)) : nullptr;
+    double *sp_prev = (p >= 1) ? wfield(st, G, Ly.sprim + (size_t)Ly.nsp * (p - 1)) : nullptr;
     double *sf_prev = (p >= 1) ? stage_face(p - 1) : nullptr;
     double *Lxy = wfield(st, G, Ly.Lxy), *EM = wfield(st, G, Ly.EM);
     const double *met = st->metric;
@@ -506,28 +526,35 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
                     shell += pts;
                 }
             }
-            a.cells = ptrs<8>(sp_prev, G.fs);
+            a.ncells = Ly.nsp;
+            a.faces_cc = glm;
+            a.cells = ptrs<10>(sp_prev, G.fs);
+            if (!glm) a.cells.p[8] = a.cells.p[9] = nullptr;
             a.faces = ptrs<3>(sf_prev, G.fs);
             a.gd.x = a.sb[a.nslab];
             a.gd.y = a.gd.z = 1;
-            pl.gh_bytes = 8.0 * shell * 11 * 2;
+            pl.gh_bytes = 8.0 * shell * (Ly.nsp + 3) * 2;
         }
         // x/y phases: reads 8 stage fields, 3 face fields, the metric; writes 8
         pl.xy = true;
         XyArgs &x = pl.xya;
         x.G = G;
         x.P = P;
-        x.sp = cptrs<8>(sp_prev, G.fs);
+        x.sp = cptrs<10>(sp_prev, G.fs);
+        if (!glm) x.sp.p[8] = x.sp.p[9] = nullptr;
         x.sf = cptrs<3>(sf_prev, G.fs);
         x.met = cptrs<2>(met, G.fs);
-        x.Lxy = ptrs<8>(Lxy, G.fs);
+        x.Lxy = ptrs<13>(Lxy, G.fs);
+        if (!glm)
+            for (int v = 8; v < 13; v++) x.Lxy.p[v] = nullptr;
         const int TX = kXyTX[V.xy], TY = kXyTY[V.xy];
         x.gd.x = (G.n[0] + TX - 1) / TX;
         x.gd.y = (G.n[1] + TY - 1) / TY;
         x.gd.z = G.n[2];
-        pl.xy_bytes = 8.0 * ncell * (8 + 3 + 2 * MET + 8);
+        pl.xy_bytes = 8.0 * ncell * (Ly.nsp + 3 + 2 * MET + Ly.nLxy);
         // EMFs: reads E_k, two face fields and the metric per edge; writes one
-        for (int i = 0; i < 3; i++) {
+        // (CT only: GLM evolves the cell-centred B with the other fluxes)
+        for (int i = 0; i < 3 && !glm; i++) {
             const int K = kCtOrder[i], a = (K + 1) % 3, b = (K + 2) % 3;
             if (!G.act[a] && !G.act[b]) continue;
             pl.ct[i] = true;
@@ -552,7 +579,7 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
         if (A.cL[j] != 0.0 && !(withL && j == p - 1)) nLst++;
         if (A.cR[j] != 0.0) nRst++;
     }
-    if (fin || !faces_are_n(T, p)) {
+    if ((fin || !faces_are_n(T, p)) && !glm) {
         pl.face = true;
         FaceArgs &f = pl.fa;
         f.G = G;
@@ -579,23 +606,29 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     c.A = A;
     CellIO &io = c.io;
     std::memset(&io, 0, sizeof(io));
-    for (int v = 0; v < 8; v++) io.Lxy[v] = Lxy + (size_t)v * G.fs;
-    for (int v = 0; v < 8; v++) io.spm[v] = sp_prev ? sp_prev + v * G.fs : nullptr;
+    const int nq = glm ? 13 : 8;  // explicit components
+    for (int v = 0; v < nq; v++) io.Lxy[v] = Lxy + (size_t)v * G.fs;
+    for (int v = 0; v < Ly.nsp; v++) io.spm[v] = sp_prev ? sp_prev + v * G.fs : nullptr;
     for (int d = 0; d < 3; d++) io.sfm[d] = sf_prev ? sf_prev + d * G.fs : nullptr;
     for (int j = 0; j < T.s; j++) {
-        for (int v = 0; v < 8; v++) io.Lc[j][v] = wfield(st, G, Ly.L + 11 * (size_t)j + v);
+        for (int v = 0; v < nq; v++) io.Lc[j][v] = wfield(st, G, Ly.L + (size_t)Ly.nL * j + v);
         for (int i = 0; i < 3; i++) io.Rj[j][i] = wfield(st, G, Ly.R + 3 * (size_t)j + i);
     }
     for (int d = 0; d < 3; d++) io.sfp[d] = fout + d * G.fs;
     const double *guess = (p == 0 || fin) ? st->prim : sp_prev;
     for (int v = 0; v < 5; v++) io.guess[v] = guess + v * G.fs;
-    for (int v = 0; v < 8; v++) io.q[v] = st->q + v * G.fs;
-    double *out = fin ? st->prim : wfield(st, G, Ly.sprim + 8 * (size_t)p);
-    for (int v = 0; v < (fin ? 5 : 8); v++) io.out[v] = out + v * G.fs;
+    for (int v = 0; v < (glm ? 10 : 8); v++) io.q[v] = st->q + v * G.fs;
+    if (glm)
+        for (int d = 0; d < 3; d++) {
+            io.qB[d] = st->face + d * G.fs;
+            io.sfout[d] = fin ? nullptr : stage_face(p) + d * G.fs;
+        }
+    double *out = fin ? st->prim : wfield(st, G, Ly.sprim + (size_t)Ly.nsp * p);
+    for (int v = 0; v < (fin ? 5 : Ly.nsp); v++) io.out[v] = out + v * G.fs;
     if (!fin)
         for (int i = 0; i < 3; i++) io.Rout[i] = wfield(st, G, Ly.R + 3 * (size_t)p + i);
     if (withL)
-        for (int v = 0; v < 8; v++) io.Lout[v] = wfield(st, G, Ly.L + 11 * (size_t)(p - 1) + v);
+        for (int v = 0; v < nq; v++) io.Lout[v] = wfield(st, G, Ly.L + (size_t)Ly.nL * (p - 1) + v);
     io.met[0] = met;
     io.met[1] = met ? met + G.fs : nullptr;
     io.nfail = wcounter(st);
@@ -609,10 +642,11 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     } else {
         c.gd = flat_dims(c.R);
     }
-    double cb = 8 + 3 + 2 * MET + 8 * nLst + 3 * nRst + (fin ? 1 : 3);  // q, faces, metric, L, R, guess
-    if (withL) cb += 8 + 8 + 3;                                          // Lxy, stage p-1 prims/E, faces
-    cb += fin ? (8 + 5) : (8 + 3);                                       // outputs
-    if (withL) cb += 8;                                                  // stored L
+    const int ng = glm ? 5 : 0;  // GLM: q_B, q_Psi, q_Phi read and written as well
+    double cb = 8 + 3 + 2 * MET + nq * nLst + 3 * nRst + (fin ? 1 : 3) + ng;  // q, faces, metric, L, R, guess
+    if (withL) cb += nq + Ly.nsp + 3;                                           // Lxy, stage p-1 block, faces
+    cb += fin ? (8 + 5 + ng) : (Ly.nsp + 3 + (glm ? 3 : 0));                    // outputs
+    if (withL) cb += nq;                                                        // stored L
     pl.ca_bytes = 8.0 * ncell * cb;
     return GR_OK;
 }
@@ -623,11 +657,14 @@ dim3 d3(const GridDims &g) { return dim3(g.x, g.y, g.z); }
 void launch_xy(const Variant &V, const XyArgs &a, hipStream_t s)
 {
     with_rm(V.rec, V.met, [&](auto R, auto M) {
-        with_xy(V.xy, [&](auto TX, auto TY) {
-            if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value>())
-                hipLaunchKernelGGL((k_xy<decltype(R)::value, decltype(M)::value, decltype(TX)::value,
-                                         decltype(TY)::value>),
-                                   d3(a.gd), dim3(decltype(TX)::value * decltype(TY)::value), 0, s, a);
+        with_glm(V.glm, [&](auto GL) {
+            with_xy(V.xy, [&](auto TX, auto TY) {
+                constexpr bool gl = decltype(GL)::value != 0;
+                if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value, gl>())
+                    hipLaunchKernelGGL((k_xy<decltype(R)::value, decltype(M)::value, decltype(TX)::value,
+                                             decltype(TY)::value, gl>),
+                                       d3(a.gd), dim3(decltype(TX)::value * decltype(TY)::value), 0, s, a);
+            });
         });
     });
 }
@@ -640,23 +677,33 @@ void launch_ct(const Variant &V, int K, const CtArgs &a, hipStream_t s)
         else hipLaunchKernelGGL((k_ct<r, m, 1>), d3(a.gd), dim3(kBlock), 0, s, a);
     });
 }
+// cell-pass instances: the dynamo and GLM are not combined (validated), GLM
+// uses the default z-phase tile
+template <bool XI, bool GLM, int TX>
+constexpr bool cell_compiled()
+{
+    return !(XI && GLM) && !(GLM && TX != 16 && TX != 1);
+}
 void launch_cell(const Variant &V, bool swz, const CellArgs &a, hipStream_t s)
 {
     with_rm(V.rec, V.met, [&](auto R, auto M) {
         constexpr int r = decltype(R)::value, m = decltype(M)::value;
-        auto go = [&](auto X) {
-            constexpr bool x = decltype(X)::value != 0;
+        auto go = [&](auto X, auto GL) {
+            constexpr bool x = decltype(X)::value != 0, gl = decltype(GL)::value != 0;
             if (!swz) {
-                hipLaunchKernelGGL((k_cell_update<r, m, 0, 1, 1, x>), d3(a.gd), dim3(kBlock), 0, s, a);
+                if constexpr (cell_compiled<x, gl, 1>())
+                    hipLaunchKernelGGL((k_cell_update<r, m, 0, 1, 1, x, gl>), d3(a.gd), dim3(kBlock), 0, s, a);
                 return;
             }
             with_cz(V.cz, [&](auto TX, auto TZ) {
-                hipLaunchKernelGGL((k_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value, x>), d3(a.gd),
-                                   dim3(kBlock), 0, s, a);
+                if constexpr (cell_compiled<x, gl, decltype(TX)::value>())
+                    hipLaunchKernelGGL((k_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value, x, gl>),
+                                       d3(a.gd), dim3(kBlock), 0, s, a);
             });
         };
-        if (V.xi) go(IC<1>{});
-        else go(IC<0>{});
+        if (V.glm) go(IC<0>{}, IC<1>{});
+        else if (V.xi) go(IC<1>{}, IC<0>{});
+        else go(IC<0>{}, IC<0>{});
     });
 }
 
@@ -804,21 +851,22 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
         if (cls_mask & (1u << KC_SWEEP)) {
             for (int rec = 0; rec < 3; rec++)
                 for (int met = 0; met < 2; met++)
-                    for (int t = 0; t < XY_COUNT; t++) {
-                        std::vector<const XyArgs *> a;
-                        std::vector<double> by;
-                        for (int r = 0; r < nr; r++) {
-                            const Variant &V = b->var[r];
-                            if (use[r] && pl[r].xy && V.rec == rec && V.met == met && V.xy == t) {
-                                a.push_back(&pl[r].xya);
-                                by.push_back(pl[r].xy_bytes);
+                    for (int gl = 0; gl < 2; gl++)
+                        for (int t = 0; t < XY_COUNT; t++) {
+                            std::vector<const XyArgs *> a;
+                            std::vector<double> by;
+                            for (int r = 0; r < nr; r++) {
+                                const Variant &V = b->var[r];
+                                if (use[r] && pl[r].xy && V.rec == rec && V.met == met && V.glm == gl && V.xy == t) {
+                                    a.push_back(&pl[r].xya);
+                                    by.push_back(pl[r].xy_bytes);
+                                }
                             }
+                            BLaunch L;
+                            L.cls = KC_SWEEP;
+                            L.V = Variant{rec, met, t, 0, 0, gl};
+                            add_group(stg, out, L, a, by);
                         }
-                        BLaunch L;
-                        L.cls = KC_SWEEP;
-                        L.V = Variant{rec, met, t, 0, 0};
-                        add_group(stg, out, L, a, by);
-                    }
         }
         // EMFs, grouped by (component, recon, metric)
         if (cls_mask & (1u << KC_CT)) {
@@ -858,14 +906,15 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
         if (cls_mask & (1u << KC_CELL_UPDATE)) {
             for (int rec = 0; rec < 3; rec++)
                 for (int met = 0; met < 2; met++)
-                    for (int xi = 0; xi < 2; xi++)
+                    for (int xg = 0; xg < 3; xg++)  // plain, dynamo, GLM
                         for (int sw = 0; sw < 2; sw++)
                             for (int t = 0; t < (sw ? CZ_COUNT : 1); t++) {
+                                const int xi = xg == 1, gl = xg == 2;
                                 std::vector<const CellArgs *> a;
                                 std::vector<double> by;
                                 for (int r = 0; r < nr; r++) {
                                     const Variant &V = b->var[r];
-                                    if (use[r] && V.rec == rec && V.met == met && V.xi == xi &&
+                                    if (use[r] && V.rec == rec && V.met == met && V.xi == xi && V.glm == gl &&
                                         (int)pl[r].swz == sw && (!sw || V.cz == t)) {
                                         a.push_back(&pl[r].ca);
                                         by.push_back(pl[r].ca_bytes);
@@ -873,7 +922,7 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
                                 }
                                 BLaunch L;
                                 L.cls = KC_CELL_UPDATE;
-                                L.V = Variant{rec, met, 0, t, xi};
+                                L.V = Variant{rec, met, 0, t, xi, gl};
                                 L.swz = sw;
                                 add_group(stg, out, L, a, by);
                             }
@@ -911,12 +960,15 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
         break;
     case KC_SWEEP:
         with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
-            with_xy(L.V.xy, [&](auto TX, auto TY) {
-                if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value>())
-                    hipLaunchKernelGGL((kb_xy<decltype(R)::value, decltype(M)::value, decltype(TX)::value,
-                                              decltype(TY)::value>),
-                                       grid, dim3(decltype(TX)::value * decltype(TY)::value), 0, s,
-                                       (const XyArgs *)L.args, L.start, L.n);
+            with_glm(L.V.glm, [&](auto GL) {
+                with_xy(L.V.xy, [&](auto TX, auto TY) {
+                    constexpr bool gl = decltype(GL)::value != 0;
+                    if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value, gl>())
+                        hipLaunchKernelGGL((kb_xy<decltype(R)::value, decltype(M)::value, decltype(TX)::value,
+                                                  decltype(TY)::value, gl>),
+                                           grid, dim3(decltype(TX)::value * decltype(TY)::value), 0, s,
+                                           (const XyArgs *)L.args, L.start, L.n);
+                });
             });
         });
         break;
@@ -936,19 +988,23 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
         with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
             constexpr int r = decltype(R)::value, m = decltype(M)::value;
             const CellArgs *a = (const CellArgs *)L.args;
-            auto go = [&](auto X) {
-                constexpr bool x = decltype(X)::value != 0;
+            auto go = [&](auto X, auto GLx) {
+                constexpr bool x = decltype(X)::value != 0, gl = decltype(GLx)::value != 0;
                 if (!L.swz) {
-                    hipLaunchKernelGGL((kb_cell_update<r, m, 0, 1, 1, x>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+                    if constexpr (cell_compiled<x, gl, 1>())
+                        hipLaunchKernelGGL((kb_cell_update<r, m, 0, 1, 1, x, gl>), grid, dim3(kBlock), 0, s, a,
+                                           L.start, L.n);
                     return;
                 }
                 with_cz(L.V.cz, [&](auto TX, auto TZ) {
-                    hipLaunchKernelGGL((kb_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value, x>), grid,
-                                       dim3(kBlock), 0, s, a, L.start, L.n);
+                    if constexpr (cell_compiled<x, gl, decltype(TX)::value>())
+                        hipLaunchKernelGGL((kb_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value, x, gl>),
+                                           grid, dim3(kBlock), 0, s, a, L.start, L.n);
                 });
             };
-            if (L.V.xi) go(IC<1>{});
-            else go(IC<0>{});
+            if (L.V.glm) go(IC<0>{}, IC<1>{});
+            else if (L.V.xi) go(IC<1>{}, IC<0>{});
+            else go(IC<0>{}, IC<0>{});
         });
         break;
     }
@@ -1058,7 +1114,7 @@ gr_status tune(gr_batch *b, const char *cache, hipStream_t s)
         std::vector<TuneKey> keys;
         for (int r = 0; r < nr; r++) {
             const gr_grid &g = b->grids[r];
-            if (what == 1 && g.ndim < 3) continue;
+            if ((what == 1 && g.ndim < 3) || g.glm) continue;  // GLM runs keep the default tiles
             TuneKey k{what, (int)g.recon, g.metric ? 1 : 0, g.ndim};
             bool seen = false;
             for (auto &q : keys) seen |= q == k;
@@ -1068,17 +1124,17 @@ gr_status tune(gr_batch *b, const char *cache, hipStream_t s)
             std::vector<char> use(nr, 0);
             for (int r = 0; r < nr; r++) {
                 const gr_grid &g = b->grids[r];
-                use[r] = ((int)g.recon == k.rec && (g.metric ? 1 : 0) == k.met && g.ndim == k.ndim);
+                use[r] = ((int)g.recon == k.rec && (g.metric ? 1 : 0) == k.met && g.ndim == k.ndim && !g.glm);
             }
+            int r0 = 0;
+            while (!use[r0]) r0++;
             int best = -1;
             for (auto &q : known)
-                if (q.first == k) best = q.second;
+                if (q.first == k && (what == 1 || xy_allowed(&b->grids[r0], q.second))) best = q.second;
             if (best < 0) {
                 double bms = 1e300;
                 const int nc = what == 0 ? XY_COUNT : CZ_COUNT;
                 for (int t = 0; t < nc && status == GR_OK; t++) {
-                    int r0 = 0;
-                    while (!use[r0]) r0++;
                     if (what == 0 && !xy_allowed(&b->grids[r0], t)) continue;
                     for (int r = 0; r < nr; r++)
                         if (use[r]) (what == 0 ? b->var[r].xy : b->var[r].cz) = t;
@@ -1159,6 +1215,9 @@ gr_status gr_validate(const gr_grid *g)
     if (!(g->gamma_ad > 1.0)) return GR_EINVAL;
     if (!std::isfinite(g->xi)) return GR_EINVAL;
     if (g->frozen_matter != 0 && g->frozen_matter != 1) return GR_EINVAL;
+    if (g->glm != 0 && g->glm != 1) return GR_EINVAL;
+    if (g->glm && (!(g->kappa_E >= 0.0) || !(g->kappa_B >= 0.0))) return GR_EINVAL;
+    if (g->glm && g->xi != 0.0) return GR_EUNSUPPORTED;  // GLM with the dynamo term: not built
     if (!(g->newton_tol > 0.0) || g->newton_maxit < 1) return GR_EINVAL;
     if (g->eta_mode == GR_ETA_UNIFORM) {
         if (!(g->eta > 0.0)) return GR_EINVAL;
@@ -1200,9 +1259,9 @@ gr_status gr_workspace_offset(const gr_grid *g, int kind, int stage, int field, 
     if (stage < 0 || stage >= T.s || !off) return GR_EINVAL;
     size_t f;
     switch (kind) {
-    case 0: if (field < 0 || field >= 8) return GR_EINVAL; f = L.sprim + 8 * (size_t)stage + field; break;
+    case 0: if (field < 0 || field >= L.nsp) return GR_EINVAL; f = L.sprim + (size_t)L.nsp * stage + field; break;
     case 1: if (field < 0 || field >= 3) return GR_EINVAL; f = L.sface + 3 * (size_t)stage + field; break;
-    case 2: if (field < 0 || field >= 11) return GR_EINVAL; f = L.L + 11 * (size_t)stage + field; break;
+    case 2: if (field < 0 || field >= L.nL) return GR_EINVAL; f = L.L + (size_t)L.nL * stage + field; break;
     case 3: if (field < 0 || field >= 3) return GR_EINVAL; f = L.R + 3 * (size_t)stage + field; break;
     default: return GR_EINVAL;
     }
@@ -1267,13 +1326,21 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
         hipLaunchKernelGGL(k_init_cons<0>, grc, blc, 0, s, G, P, Rc, cptrs<5>(st->prim, G.fs), cptrs<3>(sp0, G.fs),
                            cptrs<3>(st->face, G.fs), cptrs<2>(st->metric, G.fs), ptrs<8>(st->q, G.fs));
     LAUNCHCHK();
+    if (g->glm) {
+        // cell-centred q_B from the faces; q_Psi = q_Phi = 0
+        HIPCHK(hipMemcpyAsync(scratch, st->face, 3 * G.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_face_to_cell, gr, bl, 0, s, G, cptrs<3>(scratch, G.fs), ptrs<3>(st->face, G.fs));
+        LAUNCHCHK();
+        HIPCHK(hipMemsetAsync(st->q + 8 * G.fs, 0, 2 * G.fs * sizeof(double), s));
+    }
     // every stage block starts as a copy of the state (ghost points of fixed
     // boundaries keep these values)
     for (int j = 0; j < T.s; j++) {
-        double *spj = wfield(st, G, Ly.sprim + 8 * (size_t)j);
+        double *spj = wfield(st, G, Ly.sprim + (size_t)Ly.nsp * j);
         hipLaunchKernelGGL(k_stage_copy, gr, bl, 0, s, G, g->metric, cptrs<5>(st->prim, G.fs), cptrs<8>(st->q, G.fs),
                            cptrs<2>(st->metric, G.fs), ptrs<8>(spj, G.fs));
         LAUNCHCHK();
+        if (g->glm) HIPCHK(hipMemsetAsync(spj + 8 * G.fs, 0, 2 * G.fs * sizeof(double), s));  // Psi, Phi
         HIPCHK(hipMemcpyAsync(wfield(st, G, Ly.sface + 3 * (size_t)j), st->face, 3 * G.fs * sizeof(double),
                               hipMemcpyDeviceToDevice, s));
     }
@@ -1319,7 +1386,9 @@ gr_status gr_con2prim(const gr_grid *g, gr_state *st, hipStream_t s)
     std::memset(&io, 0, sizeof(io));
     for (int d = 0; d < 3; d++) io.sfp[d] = st->face + d * G.fs;
     for (int v5 = 0; v5 < 5; v5++) io.guess[v5] = st->prim + v5 * G.fs;
-    for (int v8 = 0; v8 < 8; v8++) io.q[v8] = st->q + v8 * G.fs;
+    for (int v8 = 0; v8 < (g->glm ? 10 : 8); v8++) io.q[v8] = st->q + v8 * G.fs;
+    if (g->glm)
+        for (int d = 0; d < 3; d++) io.qB[d] = st->face + d * G.fs;
     for (int v5 = 0; v5 < 5; v5++) io.out[v5] = st->prim + v5 * G.fs;
     io.met[0] = st->metric;
     io.met[1] = st->metric ? st->metric + G.fs : nullptr;
@@ -1331,8 +1400,16 @@ gr_status gr_con2prim(const gr_grid *g, gr_state *st, hipStream_t s)
     ca.A = A;
     ca.io = io;
     ca.gd = flat_dims(ca.R);
-    if (g->metric) hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 1, 0, 1, 1, false>), d3(ca.gd), dim3(kBlock), 0, s, ca);
-    else hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 0, 0, 1, 1, false>), d3(ca.gd), dim3(kBlock), 0, s, ca);
+    if (g->glm) {
+        if (g->metric)
+            hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 1, 0, 1, 1, false, true>), d3(ca.gd), dim3(kBlock), 0, s, ca);
+        else
+            hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 0, 0, 1, 1, false, true>), d3(ca.gd), dim3(kBlock), 0, s, ca);
+    } else if (g->metric) {
+        hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 1, 0, 1, 1, false, false>), d3(ca.gd), dim3(kBlock), 0, s, ca);
+    } else {
+        hipLaunchKernelGGL((k_cell_update<GR_MINMOD, 0, 0, 1, 1, false, false>), d3(ca.gd), dim3(kBlock), 0, s, ca);
+    }
     LAUNCHCHK();
     return GR_OK;
 }
@@ -1348,7 +1425,14 @@ gr_status gr_divB_norm(const gr_grid *g, const gr_state *st, double *out3, hipSt
     FlatBox B = flatbox(G);
     unsigned nb = nblocks(B.total);
     double *part = wparts(st);
-    hipLaunchKernelGGL(k_divb_partial, dim3(nb), dim3(256), 0, s, G, B, cptrs<3>(st->face, G.fs), part);
+    if (g->glm) {
+        BcArgs Bc;
+        for (int d = 0; d < 3; d++)
+            for (int e = 0; e < 2; e++) Bc.bc[d][e] = g->bc[d][e];
+        hipLaunchKernelGGL(k_divb_cc_partial, dim3(nb), dim3(256), 0, s, G, B, Bc, cptrs<3>(st->face, G.fs), part);
+    } else {
+        hipLaunchKernelGGL(k_divb_partial, dim3(nb), dim3(256), 0, s, G, B, cptrs<3>(st->face, G.fs), part);
+    }
     LAUNCHCHK();
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (int)nb, B.total, 0, part, out3);
     LAUNCHCHK();
@@ -1362,6 +1446,7 @@ gr_status gr_clean_divB(const gr_grid *g, gr_state *st, int vcycles, double *out
     v = check_state(g, st);
     if (v != GR_OK) return v;
     if (vcycles < 0 || vcycles > 1000) return GR_EINVAL;
+    if (g->glm) return GR_EUNSUPPORTED;  // the projection acts on face fields
     Geo G = make_geo(g);
     Layout Ly = layout(g);
     MgLevel lv[kMgMaxLevels];

@@ -26,6 +26,7 @@ struct Phys {
     double eta, sigma0, eta_min, eta_max;
     double xi;   // mean-field dynamo coefficient (eq. ohms_law)
     int frozen;  // 1: primitives fixed, only E and B evolve
+    double kappa_E, kappa_B;  // GLM damping (Sec 3.1)
 };
 
 // flat-frame primitive state -> conserved (D, S, tau, E) and the flux in
@@ -69,9 +70,10 @@ __device__ __forceinline__ void flat_cons_flux(const Phys &P, int d, double rho,
 // HLL with unit speeds, F = (f_L + f_R)/2 - (q_R - q_L)/2, accumulated one
 // state at a time: F += (f + sgn q)/2 with sgn = +1 for the left state and -1
 // for the right one (only one state's variables are live at a time)
-template <int d>
+template <int d, bool GLM = false>
 __device__ __forceinline__ void hll_accumulate(const Phys &P, double rho, const double u[3], double p,
-                                               const double E[3], const double B[3], double sgn, double F[8])
+                                               const double E[3], const double B[3], double sgn, double F[],
+                                               double Psi = 0.0, double Phi = 0.0)
 {
     constexpr int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
     double W = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -92,6 +94,15 @@ __device__ __forceinline__ void hll_accumulate(const Phys &P, double rho, const 
     F[5 + d] += 0.5 * sgn * E[d];
     F[5 + d1] += 0.5 * (B[d2] + sgn * E[d1]);
     F[5 + d2] += 0.5 * (-B[d1] + sgn * E[d2]);
+    if (GLM) {
+        // GLM (Sec 3.1): Faraday flux of the cell-centred B (the normal
+        // component has none), f_Psi = E^d, f_Phi = B^d
+        F[8 + d] += 0.5 * sgn * B[d];
+        F[8 + d1] += 0.5 * (-E[d2] + sgn * B[d1]);
+        F[8 + d2] += 0.5 * (E[d1] + sgn * B[d2]);
+        F[11] += 0.5 * (E[d] + sgn * Psi);
+        F[12] += 0.5 * (B[d] + sgn * Phi);
+    }
 }
 
 // resistivity of a cell: uniform, or 1/sigma_c of eq. sigma_D clamped to

@@ -20,41 +20,9 @@ namespace gr {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
-// ghost points: a per-direction index map composed over x, y, z equals
-// filling x, then y, then z over the full extent of the other directions
-struct BcArgs {
-    int bc[3][2];
-};
-
-__device__ __forceinline__ int map_cell(const Geo &G, const BcArgs &B, int d, int m)
-{
-    if (!G.act[d]) return m;
-    int g = G.g[d], n = G.n[d];
-    if (m < g) {
-        int b = B.bc[d][0];
-        return b == GR_OUTFLOW ? g : (b == GR_PERIODIC ? m + n : m);
-    }
-    if (m >= g + n) {
-        int b = B.bc[d][1];
-        return b == GR_OUTFLOW ? g + n - 1 : (b == GR_PERIODIC ? m - n : m);
-    }
-    return m;
-}
-// normal face field of direction d: faces g .. g+n are evolved
-__device__ __forceinline__ int map_face(const Geo &G, const BcArgs &B, int d, int m)
-{
-    if (!G.act[d]) return m;
-    int g = G.g[d], n = G.n[d];
-    if (m < g) {
-        int b = B.bc[d][0];
-        return b == GR_OUTFLOW ? g : (b == GR_PERIODIC ? m + n : m);
-    }
-    if (m > g + n) {
-        int b = B.bc[d][1];
-        return b == GR_OUTFLOW ? g + n : (b == GR_PERIODIC ? m - n : m);
-    }
-    return m;
-}
+// ghost points: the per-direction index maps map_cell / map_face (common.h)
+// composed over x, y, z equal filling x, then y, then z over the full extent
+// of the other directions
 
 // the ghost shell as up to six slabs (z low/high over the whole x-y extent,
 // y low/high inside the interior z range, x low/high inside the interior
@@ -65,7 +33,9 @@ struct GhostArgs {
     Region slab[6];
     unsigned sb[7];
     int nslab;
-    Ptr<8> cells;
+    int ncells;    // 8, or 10 with GLM (Psi, Phi)
+    int faces_cc;  // GLM: the three "face" fields are cell centred
+    Ptr<10> cells;
     Ptr<3> faces;
     GridDims gd;
 };
@@ -73,7 +43,7 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &a, Blk blk)
 {
     const Geo &G = a.G;
     const BcArgs &B = a.B;
-    const Ptr<8> &cells = a.cells;
+    const Ptr<10> &cells = a.cells;
     const Ptr<3> &faces = a.faces;
     const unsigned L = blk.x;
     int k = 0;
@@ -99,7 +69,16 @@ __device__ __forceinline__ void ghost_body(const GhostArgs &a, Blk blk)
         unsigned os = (unsigned)lin(G, s) << 3;
 #pragma unroll
         for (int v = 0; v < 8; v++) stb(cells.p[v], o, ldb(cells.p[v], os));
+        if (a.ncells > 8) {
+            stb(cells.p[8], o, ldb(cells.p[8], os));
+            stb(cells.p[9], o, ldb(cells.p[9], os));
+        }
+        if (a.faces_cc) {
+#pragma unroll
+            for (int f = 0; f < 3; f++) stb(faces.p[f], o, ldb(faces.p[f], os));
+        }
     }
+    if (a.faces_cc) return;
 #pragma unroll
     for (int f = 0; f < 3; f++) {
         int sf[3];
@@ -123,44 +102,44 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---------------------------------------------------------------------------
 // HLL flux at one face of direction D from the reconstructed states of the
-// ten face variables (rho, u~^x,y,z, p, E^x,y,z, B^t1, B^t2; reading R9), the
+// face variables (rho, u~^x,y,z, p, E^x,y,z, B^t1, B^t2; reading R9), the
 // face metric and the normal face field (Sec 2.1, Sec 2.5).  The orthonormal
 // frame makes the flux the special-relativistic one; the coordinate flux of
 // the densitised variables is that times alpha psi^4 (D, tau), alpha psi^6
-// (S) or alpha psi^2 (E).
-template <int MET, int D>
-__device__ __forceinline__ void hll_face(const Phys &P, const double sL[10], const double sR[10], double al, double ps,
-                                         double bn, double Fout[8])
+// (S) or alpha psi^2 (E).  GLM (Sec 3.1): three more variables B^D, Psi, Phi
+// are reconstructed (the normal B is no longer a face value) and the flux
+// has 13 components (+ q_B at alpha psi^2, q_Psi and q_Phi at alpha psi^4).
+template <bool GLM>
+struct NVar {
+    static constexpr int NV = GLM ? 13 : 10;  // reconstructed variables
+    static constexpr int NF = GLM ? 13 : 8;   // conserved fields with a flux
+};
+
+template <int MET, int D, bool GLM = false>
+__device__ __forceinline__ void hll_face(const Phys &P, const double *sL, const double *sR, double al, double ps,
+                                         double bn, double *Fout)
 {
     constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+    constexpr int NF = NVar<GLM>::NF;
     double ps2 = MET ? ps * ps : 1.0;
-    if (MET) bn *= frcp(ps2 * ps2 * ps2);
-    double h[8];
+    if (MET && !GLM) bn *= frcp(ps2 * ps2 * ps2);
+    double h[NF];
 #pragma unroll
-    for (int v = 0; v < 8; v++) h[v] = 0.0;
-    {
+    for (int v = 0; v < NF; v++) h[v] = 0.0;
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+        const double *st = side ? sR : sL;
         double u[3], E[3], B[3];
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            u[i] = ps2 * sL[1 + i];
-            E[i] = ps2 * sL[5 + i];
+            u[i] = ps2 * st[1 + i];
+            E[i] = ps2 * st[5 + i];
         }
-        B[D] = ps2 * bn;
-        B[t1] = ps2 * sL[8];
-        B[t2] = ps2 * sL[9];
-        hll_accumulate<D>(P, sL[0], u, sL[4], E, B, 1.0, h);
-    }
-    {
-        double u[3], E[3], B[3];
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            u[i] = ps2 * sR[1 + i];
-            E[i] = ps2 * sR[5 + i];
-        }
-        B[D] = ps2 * bn;
-        B[t1] = ps2 * sR[8];
-        B[t2] = ps2 * sR[9];
-        hll_accumulate<D>(P, sR[0], u, sR[4], E, B, -1.0, h);
+        B[D] = ps2 * (GLM ? st[10] : bn);
+        B[t1] = ps2 * st[8];
+        B[t2] = ps2 * st[9];
+        if (GLM) hll_accumulate<D, true>(P, st[0], u, st[4], E, B, side ? -1.0 : 1.0, h, st[11], st[12]);
+        else hll_accumulate<D>(P, st[0], u, st[4], E, B, side ? -1.0 : 1.0, h);
     }
     double sD = 1.0, sS = 1.0, sE = 1.0;
     if (MET) {
@@ -170,20 +149,21 @@ __device__ __forceinline__ void hll_face(const Phys &P, const double sL[10], con
         sE = al * ps2;
     }
 #pragma unroll
-    for (int v = 0; v < 8; v++) {
-        double sc = (v == 0 || v == 4) ? sD : (v < 4 ? sS : sE);
+    for (int v = 0; v < NF; v++) {
+        double sc = (v == 0 || v == 4 || v >= 11) ? sD : (v < 4 ? sS : sE);
         Fout[v] = sc * h[v];
     }
 }
 
-// transverse cell-centred B^t of the cell at coordinates c (contravariant,
-// mean of the two faces / psi^6); the +1 face index is kept inside the array
-template <int MET>
+// cell-centred B^t (contravariant) of the cell at coordinates c: the mean of
+// the two faces / psi^6 (the +1 face index kept inside the array), or with
+// GLM the cell value / psi^6
+template <int MET, bool GLM = false>
 __device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const CPtr<2> &met, const int c[3], int t)
 {
     unsigned o = (unsigned)lin(G, c) << 3;
     double b;
-    if (G.act[t]) {
+    if (G.act[t] && !GLM) {
         int cc[3] = {c[0], c[1], c[2]};
         if (cc[t] > G.N[t] - 2) cc[t] = G.N[t] - 2;
         unsigned o0 = (unsigned)lin(G, cc) << 3;
@@ -207,7 +187,7 @@ __device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const C
 // through the same LDS and each thread returns minus the flux difference of
 // its cell divided by dx_D.  Coordinates are clamped into the padded array;
 // results for points beyond the interior are computed but never stored.
-template <int D, int T0, int T1, int T2>
+template <int D, int T0, int T1, int T2, bool GLM = false>
 struct PhaseDims {
     static constexpr int NT = T0 * T1 * T2;
     static constexpr int H = 3;
@@ -218,26 +198,29 @@ struct PhaseDims {
     static constexpr int F0 = T0 + (D == 0), F1 = T1 + (D == 1), F2 = T2 + (D == 2);
     static constexpr int NF = F0 * F1 * F2;
     static constexpr int FS = D == 0 ? 1 : (D == 1 ? F0 : F0 * F1);
-    static constexpr int NV = 10;
+    static constexpr int NV = NVar<GLM>::NV;
+    static constexpr int NFL = NVar<GLM>::NF;
     static constexpr int LDS = NV * NRAW;  // doubles
     static_assert(NF <= 2 * NT, "at most two faces per thread");
-    static_assert(8 * NF <= NV * NRAW, "fluxes fit in the staging buffer");
+    static_assert(NFL * NF <= NV * NRAW, "fluxes fit in the staging buffer");
 };
 
-template <int REC, int MET, int D, int T0, int T1, int T2>
-__device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const CPtr<8> &sp, const CPtr<3> &sf,
-                                            const CPtr<2> &met, const int org[3], double *lds, double Ld[8])
+// stage block of the sweeps: sp holds rho, u~, p, E (8) and with GLM Psi, Phi
+// (fields 8, 9); sf the face fields (GLM: cell-centred q_B)
+template <int REC, int MET, int D, int T0, int T1, int T2, bool GLM = false>
+__device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const CPtr<10> &sp, const CPtr<3> &sf,
+                                            const CPtr<2> &met, const int org[3], double *lds, double *Ld)
 {
-    using PD = PhaseDims<D, T0, T1, T2>;
+    using PD = PhaseDims<D, T0, T1, T2, GLM>;
     constexpr int NT = PD::NT, H = PD::H, E0 = PD::E0, E1 = PD::E1, NRAW = PD::NRAW, SD = PD::SD;
-    constexpr int F0 = PD::F0, F1 = PD::F1, NF = PD::NF;
+    constexpr int F0 = PD::F0, F1 = PD::F1, NF = PD::NF, NV = PD::NV, NFL = PD::NFL;
     constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
     double(*raw)[NRAW] = reinterpret_cast<double(*)[NRAW]>(lds);
     const int tid = threadIdx.x;
 
     // every load of the staging rounds is issued before the first LDS store
     constexpr int NR = (NRAW + NT - 1) / NT;
-    double st[NR][10];
+    double st[NR][NV];
 #pragma unroll
     for (int k = 0; k < NR; k++) {
         const int l = tid + k * NT;
@@ -249,8 +232,13 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
             unsigned o = (unsigned)lin(G, c) << 3;
 #pragma unroll
             for (int v = 0; v < 8; v++) st[k][v] = ldb(sp.p[v], o);
-            st[k][8] = bcc_t<MET>(G, sf, met, c, t1);
-            st[k][9] = bcc_t<MET>(G, sf, met, c, t2);
+            st[k][8] = bcc_t<MET, GLM>(G, sf, met, c, t1);
+            st[k][9] = bcc_t<MET, GLM>(G, sf, met, c, t2);
+            if (GLM) {
+                st[k][10] = bcc_t<MET, GLM>(G, sf, met, c, D);
+                st[k][11] = ldb(sp.p[8], o);
+                st[k][12] = ldb(sp.p[9], o);
+            }
         }
     }
 #pragma unroll
@@ -258,21 +246,21 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
         const int l = tid + k * NT;
         if (l < NRAW) {
 #pragma unroll
-            for (int v = 0; v < 10; v++) raw[v][l] = st[k][v];
+            for (int v = 0; v < NV; v++) raw[v][l] = st[k][v];
         }
     }
     __syncthreads();
 
-    double Fr[2][8];
+    double Fr[2][NFL];
 #pragma unroll
     for (int k = 0; k < 2; k++) {
         const int f = tid + k * NT;
         if (k == 1 && f >= NF) break;
         int e[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
         const int r0 = (e[0] + (D == 0 ? H : 0)) + E0 * ((e[1] + (D == 1 ? H : 0)) + E1 * (e[2] + (D == 2 ? H : 0)));
-        double sL[10], sR[10];
+        double sL[NV], sR[NV];
 #pragma unroll
-        for (int v = 0; v < 10; v++) {
+        for (int v = 0; v < NV; v++) {
             double w[6];
 #pragma unroll
             for (int m = 0; m < 6; m++) w[m] = raw[v][r0 + (m - 3) * SD];
@@ -291,7 +279,7 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
             al = 0.5 * (ldb(met.p[0], om) + ldb(met.p[0], o));
             ps = 0.5 * (ldb(met.p[1], om) + ldb(met.p[1], o));
         }
-        hll_face<MET, D>(P, sL, sR, al, ps, ldb(sf.p[D], o), Fr[k]);
+        hll_face<MET, D, GLM>(P, sL, sR, al, ps, GLM ? 0.0 : ldb(sf.p[D], o), Fr[k]);
     }
     __syncthreads();
     double(*fl)[NF] = reinterpret_cast<double(*)[NF]>(lds);
@@ -300,12 +288,12 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
         const int f = tid + k * NT;
         if (k == 1 && f >= NF) break;
 #pragma unroll
-        for (int v = 0; v < 8; v++) fl[v][f] = Fr[k][v];
+        for (int v = 0; v < NFL; v++) fl[v][f] = Fr[k][v];
     }
     __syncthreads();
     const int f0 = (tid % T0) + F0 * (((tid / T0) % T1) + F1 * (tid / (T0 * T1)));
 #pragma unroll
-    for (int v = 0; v < 8; v++) Ld[v] = -(fl[v][f0 + PD::FS] - fl[v][f0]) * G.idx[D];
+    for (int v = 0; v < NFL; v++) Ld[v] = -(fl[v][f0 + PD::FS] - fl[v][f0]) * G.idx[D];
     __syncthreads();  // the buffer is free for the next phase
 }
 
@@ -315,45 +303,48 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
 struct XyArgs {
     Geo G;
     Phys P;
-    CPtr<8> sp;
+    CPtr<10> sp;
     CPtr<3> sf;
     CPtr<2> met;
-    Ptr<8> Lxy;
+    Ptr<13> Lxy;
     GridDims gd;
 };
-template <int REC, int MET, int TX, int TY>
+template <int REC, int MET, int TX, int TY, bool GLM>
 __device__ __forceinline__ void xy_body(const XyArgs &a, Blk blk)
 {
     const Geo &G = a.G;
-    constexpr int LX = PhaseDims<0, TX, TY, 1>::LDS, LY = PhaseDims<1, TX, TY, 1>::LDS;
+    // TY == 1 tiles serve 1-D grids only: no y phase, LDS for the x phase
+    constexpr bool HASY = TY > 1;
+    constexpr int LX = PhaseDims<0, TX, TY, 1, GLM>::LDS, LY = HASY ? PhaseDims<1, TX, TY, 1, GLM>::LDS : 1;
+    constexpr int NFL = NVar<GLM>::NF;
     __shared__ double lds[LX > LY ? LX : LY];
     const unsigned bx = blk.x, by = blk.y, bz = blk.z;
     const int org[3] = {G.g[0] + (int)bx * TX, G.g[1] + (int)by * TY, G.g[2] + (int)bz};
-    double L[8];
-    sweep_phase<REC, MET, 0, TX, TY, 1>(G, a.P, a.sp, a.sf, a.met, org, lds, L);
-    if (G.act[1]) {
-        double Ly[8];
-        sweep_phase<REC, MET, 1, TX, TY, 1>(G, a.P, a.sp, a.sf, a.met, org, lds, Ly);
+    double L[NFL];
+    sweep_phase<REC, MET, 0, TX, TY, 1, GLM>(G, a.P, a.sp, a.sf, a.met, org, lds, L);
+    if (HASY && G.act[1]) {
+        double Ly[NFL];
+        sweep_phase<REC, MET, 1, TX, TY, 1, GLM>(G, a.P, a.sp, a.sf, a.met, org, lds, Ly);
 #pragma unroll
-        for (int v = 0; v < 8; v++) L[v] += Ly[v];
+        for (int v = 0; v < NFL; v++) L[v] += Ly[v];
     }
     const int c[3] = {org[0] + (int)threadIdx.x % TX, org[1] + (int)threadIdx.x / TX, org[2]};
     if (c[0] >= G.g[0] + G.n[0] || c[1] >= G.g[1] + G.n[1]) return;
     const unsigned o = (unsigned)lin(G, c) << 3;
 #pragma unroll
-    for (int v = 0; v < 8; v++) stb(a.Lxy.p[v], o, L[v]);
+    for (int v = 0; v < NFL; v++) stb(a.Lxy.p[v], o, L[v]);
 }
-template <int REC, int MET, int TX, int TY>
+template <int REC, int MET, int TX, int TY, bool GLM>
 __global__ void __launch_bounds__(TX *TY) k_xy(XyArgs a)
 {
-    xy_body<REC, MET, TX, TY>(a, blk_of(hw_linear<true>(), a.gd));
+    xy_body<REC, MET, TX, TY, GLM>(a, blk_of(hw_linear<true>(), a.gd));
 }
-template <int REC, int MET, int TX, int TY>
+template <int REC, int MET, int TX, int TY, bool GLM>
 __global__ void __launch_bounds__(TX *TY) kb_xy(const XyArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
 {
     unsigned lb;
     const XyArgs &a = aa[batch_locate<true>(start, n, lb)];
-    xy_body<REC, MET, TX, TY>(a, blk_of(lb, a.gd));
+    xy_body<REC, MET, TX, TY, GLM>(a, blk_of(lb, a.gd));
 }
 
 template <int MET>
@@ -598,26 +589,32 @@ __global__ void __launch_bounds__(kBlock)
 
 // ---------------------------------------------------------------------------
 // cell pass
+// Field counts: 8 cell conserved variables; with GLM also q_B (3, cell
+// centred) and q_Psi, q_Phi, i.e. 13 explicit components (L index 8..10 for
+// q_B, 11..12 for q_Psi, q_Phi), stage blocks of 10 (prims, E, Psi, Phi).
 struct CellIO {
-    const double *Lxy[8];    // -(dF_x/dx + dF_y/dy) of stage p-1 (if withL)
-    const double *spm[8];    // stage p-1 primitives + E (if withL)
-    const double *sfm[3];    // stage p-1 faces (if withL)
-    const double *Lc[4][8];  // stored cell L of stages j < p
-    const double *Rj[4][3];  // stored R of stages j < p
-    const double *sfp[3];    // faces of this pass
-    const double *guess[5];  // primitives giving the Newton / recovery guess
-    double *q[8];            // state conserved variables (read; written by the final pass)
-    double *out[8];          // stage p prims + E, or state prims (final)
-    double *Rout[3];         // R of this stage
-    double *Lout[8];         // stored cell L of stage p-1 (if storeL)
+    const double *Lxy[13];    // -(dF_x/dx + dF_y/dy) of stage p-1 (if withL)
+    const double *spm[10];    // stage p-1 primitives + E (+ Psi, Phi) (if withL)
+    const double *sfm[3];     // stage p-1 faces / GLM cell q_B (if withL)
+    const double *Lc[4][13];  // stored cell L of stages j < p
+    const double *Rj[4][3];   // stored R of stages j < p
+    const double *sfp[3];     // faces of this pass (CT)
+    const double *guess[5];   // primitives giving the Newton / recovery guess
+    double *q[10];            // state conserved variables (read; written by the final pass)
+    double *qB[3];            // GLM: state cell q_B (read; written by the final pass)
+    double *sfout[3];         // GLM: stage p cell q_B (not in the final pass)
+    double *out[10];          // stage p prims + E (+ Psi, Phi), or state prims (final)
+    double *Rout[3];          // R of this stage
+    double *Lout[13];         // stored cell L of stage p-1 (if storeL)
     const double *met[2];
     unsigned long long *nfail;
 };
 
-template <int MET>
+template <int MET, bool GLM = false>
 __device__ __forceinline__ double bcc_dev(const Geo &G, const double *const *face, double ip6, unsigned o, int t)
 {
-    double v = G.act[t] ? 0.5 * (ldb(face[t], o) + ldb(face[t], o + ((unsigned)G.st[t] << 3))) : ldb(face[t], o);
+    double v = (G.act[t] && !GLM) ? 0.5 * (ldb(face[t], o) + ldb(face[t], o + ((unsigned)G.st[t] << 3)))
+                                  : ldb(face[t], o);
     return MET ? v * ip6 : v;
 }
 
@@ -632,7 +629,7 @@ struct CellArgs {
     CellIO io;
     GridDims gd;
 };
-template <int REC, int MET, int SWZ, int TX, int TZ, bool XI>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM>
 __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
 {
     const Geo &G = args.G;
@@ -640,21 +637,22 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     const Region &R = args.R;
     const StageArgs &A = args.A;
     const CellIO &io = args.io;
+    constexpr int NQ = NVar<GLM>::NF;
     int c[3];
-    double Lz[8];
+    double Lz[NQ];
     if (SWZ) {
-        __shared__ double lds[SWZ ? PhaseDims<2, TX, 1, TZ>::LDS : 1];
+        __shared__ double lds[SWZ ? PhaseDims<2, TX, 1, TZ, GLM>::LDS : 1];
         const int org[3] = {R.lo[0] + (int)blk.x * TX, R.lo[1] + (int)blk.y, R.lo[2] + (int)blk.z * TZ};
-        CPtr<8> sp;
+        CPtr<10> sp;
         CPtr<3> sf;
         CPtr<2> met;
 #pragma unroll
-        for (int v = 0; v < 8; v++) sp.p[v] = io.spm[v];
+        for (int v = 0; v < 10; v++) sp.p[v] = io.spm[v];
 #pragma unroll
         for (int d = 0; d < 3; d++) sf.p[d] = io.sfm[d];
         met.p[0] = io.met[0];
         met.p[1] = io.met[1];
-        sweep_phase<REC, MET, 2, TX, 1, TZ>(G, P, sp, sf, met, org, lds, Lz);
+        sweep_phase<REC, MET, 2, TX, 1, TZ, GLM>(G, P, sp, sf, met, org, lds, Lz);
         c[0] = org[0] + (int)threadIdx.x % TX;
         c[1] = org[1];
         c[2] = org[2] + (int)threadIdx.x / TX;
@@ -670,10 +668,10 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     }
     const double ps2 = ps * ps, ps4 = ps2 * ps2, ps6 = ps4 * ps2;
     const double ips6 = MET ? frcp(ps6) : 1.0, ips2 = MET ? frcp(ps2) : 1.0;
-    double Lc[8];
+    double Lc[NQ];
     if (A.withL) {
 #pragma unroll
-        for (int v = 0; v < 8; v++) Lc[v] = SWZ ? ldb(io.Lxy[v], o) + Lz[v] : ldb(io.Lxy[v], o);
+        for (int v = 0; v < NQ; v++) Lc[v] = SWZ ? ldb(io.Lxy[v], o) + Lz[v] : ldb(io.Lxy[v], o);
         double rho = ldb(io.spm[0], o), pr = ldb(io.spm[4], o);
         double u[3] = {ps2 * ldb(io.spm[1], o), ps2 * ldb(io.spm[2], o), ps2 * ldb(io.spm[3], o)};
         double W = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -698,12 +696,29 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         // non-stiff current: s_E = -alpha psi^6 rho_e v^i = -alpha psi^4 rho_e v_on
 #pragma unroll
         for (int i = 0; i < 3; i++) Lc[5 + i] -= al * ps4 * rhoe * v[i];
+        if (GLM) {
+            // GLM sources (Sec 3.1): -alpha psi^6 gamma^{ij} d_j Psi (q_E) and
+            // d_j Phi (q_B), damping and charge of Psi, Phi; the lapse
+            // gradient terms follow in the metric block
+            const double Psic = ldb(io.spm[8], o), Phic = ldb(io.spm[9], o);
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                if (!G.act[d]) continue;
+                unsigned sd = (unsigned)G.st[d] << 3;
+                double dPsi = (ldb(io.spm[8], o + sd) - ldb(io.spm[8], o - sd)) * (0.5 * G.idx[d]);
+                double dPhi = (ldb(io.spm[9], o + sd) - ldb(io.spm[9], o - sd)) * (0.5 * G.idx[d]);
+                Lc[5 + d] -= al * ps2 * dPsi;
+                Lc[8 + d] -= al * ps2 * dPhi;
+            }
+            Lc[11] += ps6 * al * (rhoe - P.kappa_E * Psic);
+            Lc[12] -= ps6 * al * P.kappa_B * Phic;
+        }
         if (MET) {
             double E[3], B[3];
 #pragma unroll
             for (int i = 0; i < 3; i++) {
                 E[i] = ps2 * ldb(io.spm[5 + i], o);
-                B[i] = ps2 * bcc_dev<MET>(G, io.sfm, ips6, o, i);
+                B[i] = ps2 * bcc_dev<MET, GLM>(G, io.sfm, ips6, o, i);
             }
             double w = (rho + P.G1 * pr) * W * W;
             double U = 0.5 * (E[0] * E[0] + E[1] * E[1] + E[2] * E[2] + B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
@@ -721,19 +736,30 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
                 // s_S = psi^6 [-(tau + D) d alpha + 2 alpha (d psi / psi) tr Pi]
                 Lc[1 + d] += ps6 * (-tauD * da + 2.0 * al * dp * ips * trPi);
                 sdt -= S[d] * da;
+                if (GLM) {
+                    // psi^6 E^i d_i alpha = psi^4 E_on d alpha, likewise for B
+                    Lc[11] += ps4 * E[d] * da;
+                    Lc[12] += ps4 * B[d] * da;
+                }
             }
             // s_tau = -psi^6 S^j d_j alpha = -psi^4 S_on . grad alpha
             Lc[4] += ps4 * sdt;
         }
         if (A.storeL) {
 #pragma unroll
-            for (int v8 = 0; v8 < 8; v8++) stb(io.Lout[v8], o, Lc[v8]);
+            for (int v8 = 0; v8 < NQ; v8++) stb(io.Lout[v8], o, Lc[v8]);
         }
     }
     // accumulation q* = q^n + dt sum_j (cL_j L_j + cR_j R_j)
-    double qs[8];
+    double qs[NQ];
 #pragma unroll
     for (int v = 0; v < 8; v++) qs[v] = ldb(io.q[v], o);
+    if (GLM) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) qs[8 + i] = ldb(io.qB[i], o);
+        qs[11] = ldb(io.q[8], o);
+        qs[12] = ldb(io.q[9], o);
+    }
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         if (j >= A.p) continue;
@@ -741,10 +767,10 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
             double w = A.dt * A.cL[j];
             if (A.withL && j == A.p - 1) {
 #pragma unroll
-                for (int v = 0; v < 8; v++) qs[v] += w * Lc[v];
+                for (int v = 0; v < NQ; v++) qs[v] += w * Lc[v];
             } else {
 #pragma unroll
-                for (int v = 0; v < 8; v++) qs[v] += w * ldb(io.Lc[j][v], o);
+                for (int v = 0; v < NQ; v++) qs[v] += w * ldb(io.Lc[j][v], o);
             }
         }
         if (A.cR[j] != 0.0) {
@@ -755,8 +781,25 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     }
     // orthonormal frame: B of this pass, D, tau, S, E*
     double B[3];
+    if (GLM) {
+        // the explicit stage value of the cell-centred q_B; Psi, Phi of the stage
 #pragma unroll
-    for (int i = 0; i < 3; i++) B[i] = ps2 * bcc_dev<MET>(G, io.sfp, ips6, o, i);
+        for (int i = 0; i < 3; i++) B[i] = ps2 * qs[8 + i] * ips6;
+        if (A.fin) {
+#pragma unroll
+            for (int i = 0; i < 3; i++) stb(io.qB[i], o, qs[8 + i]);
+            stb(io.q[8], o, qs[11]);
+            stb(io.q[9], o, qs[12]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; i++) stb(io.sfout[i], o, qs[8 + i]);
+            stb(io.out[8], o, qs[11] * ips6);
+            stb(io.out[9], o, qs[12] * ips6);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; i++) B[i] = ps2 * bcc_dev<MET>(G, io.sfp, ips6, o, i);
+    }
     const double ips8 = ips6 * ips2;
     double D = qs[0] * ips6, tau = qs[4] * ips6;
     double S[3] = {qs[1] * ips8, qs[2] * ips8, qs[3] * ips8};
@@ -899,18 +942,18 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     }
     if (status == 2) atomicAdd(io.nfail, 1ull);
 }
-template <int REC, int MET, int SWZ, int TX, int TZ, bool XI>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM>
 __global__ void __launch_bounds__(kBlock) k_cell_update(CellArgs a)
 {
-    cell_body<REC, MET, SWZ, TX, TZ, XI>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
+    cell_body<REC, MET, SWZ, TX, TZ, XI, GLM>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
 }
-template <int REC, int MET, int SWZ, int TX, int TZ, bool XI>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM>
 __global__ void __launch_bounds__(kBlock)
     kb_cell_update(const CellArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
 {
     unsigned lb;
     const CellArgs &a = aa[batch_locate<SWZ != 0>(start, n, lb)];
-    cell_body<REC, MET, SWZ, TX, TZ, XI>(a, blk_of(lb, a.gd));
+    cell_body<REC, MET, SWZ, TX, TZ, XI, GLM>(a, blk_of(lb, a.gd));
 }
 
 }  // namespace gr

@@ -34,7 +34,8 @@ class gr_grid(ctypes.Structure):
                 ("sigma0", ctypes.c_double), ("eta_min", ctypes.c_double), ("eta_max", ctypes.c_double),
                 ("rho_atm", ctypes.c_double), ("p_atm", ctypes.c_double), ("metric", ctypes.c_int),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int), ("xi", ctypes.c_double),
-                ("atm_factor", ctypes.c_double), ("frozen_matter", ctypes.c_int)]
+                ("atm_factor", ctypes.c_double), ("frozen_matter", ctypes.c_int), ("glm", ctypes.c_int),
+                ("kappa_E", ctypes.c_double), ("kappa_B", ctypes.c_double)]
 
 
 class gr_state(ctypes.Structure):
@@ -260,6 +261,9 @@ def grid_of(s) -> gr_grid:
     g.xi = s.xi
     g.atm_factor = s.atm_factor
     g.frozen_matter = s.frozen_matter
+    g.glm = s.glm
+    g.kappa_E = s.kappa_E
+    g.kappa_B = s.kappa_B
     return g
 
 
@@ -277,7 +281,8 @@ class Run:
         self.fs = gr_field_stride(self.grid)
         self.np = int(np.prod(setup.shape))
         dev = torch.device(device)
-        self.q = torch.zeros(8 * self.fs, dtype=torch.float64, device=dev)
+        self.nq = 10 if setup.glm else 8
+        self.q = torch.zeros(self.nq * self.fs, dtype=torch.float64, device=dev)
         self.face = torch.zeros(3 * self.fs, dtype=torch.float64, device=dev)
         self.prim = torch.zeros(5 * self.fs, dtype=torch.float64, device=dev)
         self.metric = torch.zeros(2 * self.fs, dtype=torch.float64, device=dev) if setup.metric else None
@@ -342,7 +347,7 @@ class Run:
         return self._block(self.prim, 5)
 
     def cons(self):
-        return self._block(self.q, 8)
+        return self._block(self.q, self.nq)
 
     def faces(self):
         return self._block(self.face, 3)

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     L = grmhd.lib()
     for name in declared_symbols():
         assert hasattr(L, name), name
-    assert grmhd.gr_abi_version() == 2
+    assert grmhd.gr_abi_version() == 3
 
 
 def test_validation_rejects_bad_grids():
@@ -46,6 +46,17 @@ def test_validation_rejects_bad_grids():
     g2.frozen_matter = 2
     assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
     g2 = grmhd.grid_of(s)
+    g2.glm = 1
+    assert grmhd.gr_validate(g2) == 0  # GLM cleaning supported
+    g2.kappa_B = -1.0
+    assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
+    g2.kappa_B = 1.0
+    g2.xi = 0.1
+    assert grmhd.gr_validate(g2) == grmhd.GR_EUNSUPPORTED  # GLM with the dynamo term
+    g2.xi = 0.0
+    g2.glm = 2
+    assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
+    g2 = grmhd.grid_of(s)
     g2.bc[0][0] = W.PERIODIC  # periodic on one side only
     assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
     g2 = grmhd.grid_of(s)
@@ -55,7 +66,8 @@ def test_validation_rejects_bad_grids():
     assert grmhd.gr_workspace_bytes(g2) == 0
 
 
-@pytest.mark.parametrize("make", [lambda: W.shock_tube(400), lambda: W.blast_wave(512), lambda: W.tov_star(32)])
+@pytest.mark.parametrize("make", [lambda: W.shock_tube(400), lambda: W.blast_wave(512), lambda: W.tov_star(32),
+                                  lambda: W.glm_monopole(24, ndim=3), lambda: W.glm_wave(64)])
 def test_layout(make):
     s = make()
     g = grmhd.grid_of(s)
@@ -63,14 +75,19 @@ def test_layout(make):
     assert fs >= s.shape[0] * s.shape[1] * s.shape[2] and fs % 32 == 0
     wb = grmhd.gr_workspace_bytes(g)
     nst = 2 if s.imex == W.SSP2 else 4
+    # stage prims + E (+ Psi, Phi with GLM), stage faces, stored L (+ q_B,
+    # q_Psi, q_Phi components with GLM), stored R
+    fields = [(0, 10), (1, 3), (2, 13), (3, 3)] if s.glm else [(0, 8), (1, 3), (2, 11), (3, 3)]
     offs = set()
-    for kind, nf in [(0, 8), (1, 3), (2, 11), (3, 3)]:
+    for kind, nf in fields:
         for st in range(nst):
             for f in range(nf):
                 o = grmhd.gr_workspace_offset(g, kind, st, f)
                 assert o % 256 == 0 and o + 8 * fs <= wb
                 offs.add(o)
-    assert len(offs) == nst * 25  # no two fields share storage
+        with pytest.raises(grmhd.GrError):
+            grmhd.gr_workspace_offset(g, kind, 0, nf)
+    assert len(offs) == nst * sum(nf for _, nf in fields)  # no two fields share storage
     with pytest.raises(grmhd.GrError):
         grmhd.gr_workspace_offset(g, 0, nst, 0)
 
