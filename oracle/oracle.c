@@ -54,6 +54,8 @@ typedef struct {
     int frozen_matter;   /* 1: rho, u~, p stay fixed, only E and B evolve     */
     int glm;             /* 1: cell-centred B with GLM cleaning (Sec 3.1)     */
     double kappa_E, kappa_B; /* GLM damping parameters                        */
+    int uct;             /* 0: resistive upwind CT (Sec 3.2), 1: the ideal-MHD
+                            form of App. A (edge E from transport velocities)  */
 } or_grid;
 
 enum { BC_OUTFLOW = 0, BC_PERIODIC = 1, BC_FIXED = 2 };
@@ -837,11 +839,75 @@ static double get_face(const lctx *c, const int *cc, void *arg)
     return c->face[d][IXv(&c->q, cc)];
 }
 
+/* App. A steps (i)-(ii): the weighted transverse transport velocity
+ * bar-v^j at the d-face cf, from the reconstructed left/right states of u~
+ * there: hat-v^j = alpha v^j (beta = 0), v^j = u~^j / W, W^2 = 1 + gamma_ik
+ * u~^i u~^k with the face metric; weights c-_d hat-v_R + c+_d hat-v_L. */
+static double vbar_at_face(const lctx *c, int d, int j, const int cf[3])
+{
+    double al, ps;
+    face_metric(c, d, cf, &al, &ps);
+    double g4 = pow4(ps);
+    double uL[3], uR[3];
+    for (int i = 0; i < 3; i++) {
+        if (c->q.act[d]) {
+            recon_cells(c, d, cf, 1 + i, &uL[i], &uR[i]);
+        } else {
+            uL[i] = uR[i] = c->prim[1 + i][IXv(&c->q, cf)];
+        }
+    }
+    double WL = sqrt(1.0 + g4 * (uL[0] * uL[0] + uL[1] * uL[1] + uL[2] * uL[2]));
+    double WR = sqrt(1.0 + g4 * (uR[0] * uR[0] + uR[1] * uR[1] + uR[2] * uR[2]));
+    double vL = al * uL[j] / WL, vR = al * uR[j] / WR;
+    double cp = face_speed(c, d, cf), cm = cp;
+    return (cm * vR + cp * vL) / (cm + cp);
+}
+static double get_vbar(const lctx *c, const int *cc, void *arg)
+{
+    const int *dj = (const int *)arg;
+    return vbar_at_face(c, dj[0], dj[1], cc);
+}
+
+/* edge speeds of Sec 3.2 (vi): c_a maximised over the two a-faces sharing
+ * the edge, c_b over the two b-faces */
+static void edge_speeds(const lctx *c, int a, int b, const int ce[3], double *ca, double *cb)
+{
+    int c1[3] = {ce[0], ce[1], ce[2]}, c2[3] = {ce[0], ce[1], ce[2]};
+    if (c->q.act[b]) c1[b] -= 1;
+    *ca = fmax(face_speed(c, a, c1), face_speed(c, a, c2));
+    int c3[3] = {ce[0], ce[1], ce[2]}, c4[3] = {ce[0], ce[1], ce[2]};
+    if (c->q.act[a]) c3[a] -= 1;
+    *cb = fmax(face_speed(c, b, c3), face_speed(c, b, c4));
+}
+
+/* App. A (ideal-MHD upwind CT): hat-E_k = alpha E_k with E_k = -eps_kab v^a
+ * B^b, i.e. -eta_kab hat-v^a q_B^b.  (iii) bar-v^a of the b-faces and q_B^b
+ * are reconstructed along a to the edge, bar-v^b of the a-faces and q_B^a
+ * along b; (iv) the HLL-type combination with the speeds of each direction.
+ * Reading: the printed sqrt(gamma) factor is already inside q_B = psi^6 B. */
+static double uct_edge_ideal(const lctx *c, int k, const int ce[3])
+{
+    int a = (k + 1) % 3, b = (k + 2) % 3;
+    double vaL, vaR, qbL, qbR, vbL, vbR, qaL, qaR;
+    int fb[2] = {b, a}, fa[2] = {a, b};
+    recon_along(c, a, ce, get_vbar, fb, &vaL, &vaR);
+    recon_along(c, a, ce, get_face, &b, &qbL, &qbR);
+    recon_along(c, b, ce, get_vbar, fa, &vbL, &vbR);
+    recon_along(c, b, ce, get_face, &a, &qaL, &qaR);
+    double ca, cb;
+    edge_speeds(c, a, b, ce, &ca, &cb);
+    double cap = ca, cam = ca, cbp = cb, cbm = cb;
+    double t1 = (cam * vaR * qbR + cap * vaL * qbL - cam * cap * (qbR - qbL)) / (cam + cap);
+    double t2 = (cbm * vbR * qaR + cbp * vbL * qaL - cbm * cbp * (qaR - qaL)) / (cbm + cbp);
+    return -t1 + t2;
+}
+
 /* Sec 3.2 steps (i)-(vii): upwind EMF hat-E_k at the edge with index ce
  * (half a cell below the centre in the two directions a, b other than k;
  * (k, a, b) cyclic).  Reading: in E^{XY} the first letter is the side in a. */
 static double uct_edge(const lctx *c, int k, const int ce[3])
 {
+    if (c->G->uct == 1) return uct_edge_ideal(c, k, ce);
     int a = (k + 1) % 3, b = (k + 2) % 3;
     /* (ii)+(iii): E_k cell -> a-face (L/R), then a-face -> edge along b */
     double ELL, ELR, ERL, ERR;
@@ -853,12 +919,8 @@ static double uct_edge(const lctx *c, int k, const int ce[3])
     recon_along(c, a, ce, get_face, &b, &qbL, &qbR);
     recon_along(c, b, ce, get_face, &a, &qaL, &qaR);
     /* (vi): speeds, maximised over the two a-faces (b-faces) sharing the edge */
-    int c1[3] = {ce[0], ce[1], ce[2]}, c2[3] = {ce[0], ce[1], ce[2]};
-    if (c->q.act[b]) c1[b] -= 1;
-    double ca = fmax(face_speed(c, a, c1), face_speed(c, a, c2));
-    int c3[3] = {ce[0], ce[1], ce[2]}, c4[3] = {ce[0], ce[1], ce[2]};
-    if (c->q.act[a]) c3[a] -= 1;
-    double cb = fmax(face_speed(c, b, c3), face_speed(c, b, c4));
+    double ca, cb;
+    edge_speeds(c, a, b, ce, &ca, &cb);
     double cap = ca, cam = ca, cbp = cb, cbm = cb;
     /* lapse at the edge: mean of the surrounding cell centres */
     double asum = 0.0;

@@ -151,12 +151,15 @@ def test_star_div_b_round_off():
 
 
 # --------------------------------------------------------------------------
-def test_constant_metric_is_a_rescaled_flat_run():
+@pytest.mark.parametrize("uct", [0, 1])
+def test_constant_metric_is_a_rescaled_flat_run(uct):
     """constant lapse alpha and conformal factor psi: the conformally flat run
     equals a flat run on a domain psi^2 larger with time step alpha dt and
-    orthonormal components psi^2 (u~, E, B) (face field q_B = psi^4 B_flat)"""
+    orthonormal components psi^2 (u~, E, B) (face field q_B = psi^4 B_flat);
+    for the resistive (Sec 3.2) and the ideal-MHD (App. A) edge EMFs"""
     alpha, psi = 0.8, 1.1
     sA = W.blast_wave(16, recon=W.MC, imex=W.SSP2, steps=3)
+    sA.uct = uct
     sA.eta = 1e-2
     sA.metric = 1
     sA.alpha = np.full(sA.shape, alpha)
@@ -169,6 +172,7 @@ def test_constant_metric_is_a_rescaled_flat_run():
     stA = oracle.OracleState(sA)
     dtA = 0.02
     sB = W.blast_wave(16, recon=W.MC, imex=W.SSP2, steps=3)
+    sB.uct = uct
     sB.eta = 1e-2
     sB.lo = (-6 * psi ** 2, -6 * psi ** 2, 0)
     sB.hi = (6 * psi ** 2, 6 * psi ** 2, 1)

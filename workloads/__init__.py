@@ -60,6 +60,7 @@ class Setup:
     glm: int = 0               # 1: cell-centred B with GLM cleaning (Sec 3.1)
     kappa_E: float = 1.0
     kappa_B: float = 1.0
+    uct: int = 0               # 0 resistive upwind CT (Sec 3.2), 1 ideal-MHD form (App. A)
     steps: int = 1
     # initial data (padded arrays, see module docstring)
     prim: Optional[np.ndarray] = None      # (5, Nz, Ny, Nx)
