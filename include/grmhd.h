@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 3
+#define GR_ABI_VERSION 4
 
 typedef enum {
     GR_OK = 0,
@@ -79,6 +79,10 @@ typedef struct gr_grid {
     int frozen_matter;    /* 1: rho, u~, p stay fixed and only E and B evolve   */
     int glm;              /* 1: cell-centred B with GLM cleaning (Sec 3.1)      */
     double kappa_E, kappa_B; /* GLM damping parameters                          */
+    int uct;              /* edge EMF of the CT update: 0 the resistive upwind
+                             form (Sec 3.2, reconstructed E), 1 the ideal-MHD
+                             form (App. A, transport velocities x face fields;
+                             the eta -> 0 limit); GR_EUNSUPPORTED with glm     */
 } gr_grid;
 
 /* Device state of one run (all pointers caller-owned device memory). */

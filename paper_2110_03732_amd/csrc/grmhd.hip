@@ -357,6 +357,7 @@ struct Variant {
     int rec, met, xy, cz;
     int xi;   // mean-field dynamo terms compiled into the cell pass
     int glm;  // GLM cleaning (cell-centred B): default tiles only
+    int uct;  // 1: ideal-MHD edge EMF
 };
 // tiles a run may use: two-dimensional x/y tiles when y is active, one-row
 // tiles otherwise (the metric 1-D case only the 256-wide one)
@@ -376,6 +377,7 @@ Variant default_variant(const gr_grid *g)
     V.cz = CZ_16x16;
     V.xi = g->xi != 0.0 ? 1 : 0;
     V.glm = g->glm ? 1 : 0;
+    V.uct = g->uct ? 1 : 0;
     return V;
 }
 
@@ -418,9 +420,9 @@ constexpr bool xy_compiled()
     return !(MET == 1 && TY == 1 && TX != 256);
 }
 template <class F>
-void with_glm(int glm, F &&f)
+void with_flag(int flag, F &&f)
 {
-    if (glm) f(IC<1>{});
+    if (flag) f(IC<1>{});
     else f(IC<0>{});
 }
 
@@ -562,6 +564,7 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
             c.G = G;
             c.R = region(G, (1 << a) | (1 << b));
             c.Ek = sp_prev + (size_t)(5 + K) * G.fs;
+            c.u = cptrs<3>(sp_prev + G.fs, G.fs);
             c.sf = cptrs<3>(sf_prev, G.fs);
             c.met = cptrs<2>(met, G.fs);
             c.EM = EM + (size_t)K * G.fs;
@@ -569,7 +572,8 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
             c.gd.x = (c.R.cnt[0] + Tt[0] - 1) / Tt[0];
             c.gd.y = (c.R.cnt[1] + Tt[1] - 1) / Tt[1];
             c.gd.z = (c.R.cnt[2] + Tt[2] - 1) / Tt[2];
-            pl.ct_bytes[i] = 8.0 * rtotal(c.R) * (3 + 2 * MET + 1);
+            // ideal-MHD form: u~ (3) instead of E_k
+            pl.ct_bytes[i] = 8.0 * rtotal(c.R) * ((g->uct ? 5 : 3) + 2 * MET + 1);
         }
     }
     // faces of this pass
@@ -657,7 +661,7 @@ dim3 d3(const GridDims &g) { return dim3(g.x, g.y, g.z); }
 void launch_xy(const Variant &V, const XyArgs &a, hipStream_t s)
 {
     with_rm(V.rec, V.met, [&](auto R, auto M) {
-        with_glm(V.glm, [&](auto GL) {
+        with_flag(V.glm, [&](auto GL) {
             with_xy(V.xy, [&](auto TX, auto TY) {
                 constexpr bool gl = decltype(GL)::value != 0;
                 if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value, gl>())
@@ -671,10 +675,13 @@ void launch_xy(const Variant &V, const XyArgs &a, hipStream_t s)
 void launch_ct(const Variant &V, int K, const CtArgs &a, hipStream_t s)
 {
     with_rm(V.rec, V.met, [&](auto R, auto M) {
-        constexpr int r = decltype(R)::value, m = decltype(M)::value;
-        if (K == 2) hipLaunchKernelGGL((k_ct<r, m, 2>), d3(a.gd), dim3(kBlock), 0, s, a);
-        else if (K == 0) hipLaunchKernelGGL((k_ct<r, m, 0>), d3(a.gd), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_ct<r, m, 1>), d3(a.gd), dim3(kBlock), 0, s, a);
+        with_flag(V.uct, [&](auto U) {
+            constexpr int r = decltype(R)::value, m = decltype(M)::value;
+            constexpr bool u = decltype(U)::value != 0;
+            if (K == 2) hipLaunchKernelGGL((k_ct<r, m, 2, u>), d3(a.gd), dim3(kBlock), 0, s, a);
+            else if (K == 0) hipLaunchKernelGGL((k_ct<r, m, 0, u>), d3(a.gd), dim3(kBlock), 0, s, a);
+            else hipLaunchKernelGGL((k_ct<r, m, 1, u>), d3(a.gd), dim3(kBlock), 0, s, a);
+        });
     });
 }
 // cell-pass instances: the dynamo and GLM are not combined (validated), GLM
@@ -872,22 +879,23 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
         if (cls_mask & (1u << KC_CT)) {
             for (int i = 0; i < 3; i++)
                 for (int rec = 0; rec < 3; rec++)
-                    for (int met = 0; met < 2; met++) {
-                        std::vector<const CtArgs *> a;
-                        std::vector<double> by;
-                        for (int r = 0; r < nr; r++) {
-                            const Variant &V = b->var[r];
-                            if (use[r] && pl[r].ct[i] && V.rec == rec && V.met == met) {
-                                a.push_back(&pl[r].cta[i]);
-                                by.push_back(pl[r].ct_bytes[i]);
+                    for (int met = 0; met < 2; met++)
+                        for (int uct = 0; uct < 2; uct++) {
+                            std::vector<const CtArgs *> a;
+                            std::vector<double> by;
+                            for (int r = 0; r < nr; r++) {
+                                const Variant &V = b->var[r];
+                                if (use[r] && pl[r].ct[i] && V.rec == rec && V.met == met && V.uct == uct) {
+                                    a.push_back(&pl[r].cta[i]);
+                                    by.push_back(pl[r].ct_bytes[i]);
+                                }
                             }
+                            BLaunch L;
+                            L.cls = KC_CT;
+                            L.K = kCtOrder[i];
+                            L.V = Variant{rec, met, 0, 0, 0, 0, uct};
+                            add_group(stg, out, L, a, by);
                         }
-                        BLaunch L;
-                        L.cls = KC_CT;
-                        L.K = kCtOrder[i];
-                        L.V = Variant{rec, met, 0, 0, 0};
-                        add_group(stg, out, L, a, by);
-                    }
         }
         // face update
         if (cls_mask & (1u << KC_FACE_UPDATE)) {
@@ -960,7 +968,7 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
         break;
     case KC_SWEEP:
         with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
-            with_glm(L.V.glm, [&](auto GL) {
+            with_flag(L.V.glm, [&](auto GL) {
                 with_xy(L.V.xy, [&](auto TX, auto TY) {
                     constexpr bool gl = decltype(GL)::value != 0;
                     if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value, gl>())
@@ -974,11 +982,14 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
         break;
     case KC_CT:
         with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
-            constexpr int r = decltype(R)::value, m = decltype(M)::value;
-            const CtArgs *a = (const CtArgs *)L.args;
-            if (L.K == 2) hipLaunchKernelGGL((kb_ct<r, m, 2>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
-            else if (L.K == 0) hipLaunchKernelGGL((kb_ct<r, m, 0>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
-            else hipLaunchKernelGGL((kb_ct<r, m, 1>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+            with_flag(L.V.uct, [&](auto U) {
+                constexpr int r = decltype(R)::value, m = decltype(M)::value;
+                constexpr bool u = decltype(U)::value != 0;
+                const CtArgs *a = (const CtArgs *)L.args;
+                if (L.K == 2) hipLaunchKernelGGL((kb_ct<r, m, 2, u>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+                else if (L.K == 0) hipLaunchKernelGGL((kb_ct<r, m, 0, u>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+                else hipLaunchKernelGGL((kb_ct<r, m, 1, u>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+            });
         });
         break;
     case KC_FACE_UPDATE:
@@ -1218,6 +1229,8 @@ gr_status gr_validate(const gr_grid *g)
     if (g->glm != 0 && g->glm != 1) return GR_EINVAL;
     if (g->glm && (!(g->kappa_E >= 0.0) || !(g->kappa_B >= 0.0))) return GR_EINVAL;
     if (g->glm && g->xi != 0.0) return GR_EUNSUPPORTED;  // GLM with the dynamo term: not built
+    if (g->uct != 0 && g->uct != 1) return GR_EINVAL;
+    if (g->glm && g->uct) return GR_EUNSUPPORTED;  // GLM has no edge EMF
     if (!(g->newton_tol > 0.0) || g->newton_maxit < 1) return GR_EINVAL;
     if (g->eta_mode == GR_ETA_UNIFORM) {
         if (!(g->eta > 0.0)) return GR_EINVAL;

@@ -392,11 +392,146 @@ struct CtArgs {
     Geo G;
     Region R;
     const double *Ek;
+    CPtr<3> u;  // stage u~ (ideal-MHD form)
     CPtr<3> sf;
     CPtr<2> met;
     double *EM;
     GridDims gd;
 };
+
+// transport velocity at a d-face (App. A (i)-(ii)): hat-v^j = alpha v^j of the
+// left and right states of u~ reconstructed along d (the cell value along an
+// inactive d), weighted by the face speeds; these are equal (metric-only), so
+// the weighted velocity is the mean of the two
+template <int REC, int MET, int D, int J>
+__device__ __forceinline__ double ct_vbar(const Geo &G, const CtArgs &a, int id)
+{
+    const unsigned o = (unsigned)id << 3;
+    double al, ps;
+    face_metric<MET>(G, a.met, o, D, al, ps);
+    const double p2 = ps * ps;
+    double uL[3], uR[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        if (G.act[D]) {
+            recon_at<REC>(a.u.p[i], id, G.st[D], uL[i], uR[i]);
+        } else {
+            uL[i] = uR[i] = ldb(a.u.p[i], o);
+        }
+    }
+    // W^2 = 1 + psi^4 |u~|^2 (orthonormal u = psi^2 u~)
+    const double WL = sqrt(1.0 + p2 * p2 * (uL[0] * uL[0] + uL[1] * uL[1] + uL[2] * uL[2]));
+    const double WR = sqrt(1.0 + p2 * p2 * (uR[0] * uR[0] + uR[1] * uR[1] + uR[2] * uR[2]));
+    return 0.5 * (al * uL[J] / WL + al * uR[J] / WR);
+}
+
+// ideal-MHD upwind CT (App. A): hat-E_k = -(hat-v^a q_B^b - hat-v^b q_B^a) at
+// the edge, each product in HLL form along the direction it is reconstructed
+// in.  Step 1 stages, for the a-faces widened along b, bar-v^b and q_B^a, and
+// for the b-faces widened along a, bar-v^a; step 2 reconstructs bar-v^b and
+// q_B^a along b, bar-v^a and q_B^b along a, and combines.
+template <int REC, int MET, int K>
+__device__ __forceinline__ void ct_ideal_body(const CtArgs &args, Blk blk)
+{
+    const Geo &G = args.G;
+    const Region &R = args.R;
+    const CPtr<3> &sf = args.sf;
+    const CPtr<2> &met = args.met;
+    constexpr int A = (K + 1) % 3, B = (K + 2) % 3;
+    constexpr int T0 = CtTile<K>::T[0], T1 = CtTile<K>::T[1], T2 = CtTile<K>::T[2];
+    constexpr int HB = 3;
+    // a-faces widened along b
+    constexpr int E0 = T0 + (B == 0 ? 2 * HB : 0), E1 = T1 + (B == 1 ? 2 * HB : 0), E2 = T2 + (B == 2 ? 2 * HB : 0);
+    constexpr int NL = E0 * E1 * E2;
+    constexpr int SB = (B == 0) ? 1 : (B == 1 ? E0 : E0 * E1);
+    // b-faces widened along a
+    constexpr int F0 = T0 + (A == 0 ? 2 * HB : 0), F1 = T1 + (A == 1 ? 2 * HB : 0), F2 = T2 + (A == 2 ? 2 * HB : 0);
+    constexpr int NLA = F0 * F1 * F2;
+    constexpr int SA = (A == 0) ? 1 : (A == 1 ? F0 : F0 * F1);
+    static_assert(T0 * T1 * T2 == kBlock, "one edge per thread");
+    __shared__ double sVb[NL], sQa[NL], sVa[NLA];
+
+    const int tid = threadIdx.x;
+    const int org[3] = {R.lo[0] + (int)blk.x * T0, R.lo[1] + (int)blk.y * T1, R.lo[2] + (int)blk.z * T2};
+    const bool actA = G.act[A], actB = G.act[B];
+    auto clamp_pos = [&](const int e[3], int W, int c[3]) {
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            int lo = R.lo[d], hi = R.lo[d] + R.cnt[d] - 1;
+            c[d] = org[d] + e[d];
+            if (d == W) {
+                c[d] -= HB;
+                lo = lo - HB < 0 ? 0 : lo - HB;
+                hi = hi + HB > G.N[d] - 1 ? G.N[d] - 1 : hi + HB;
+            }
+            c[d] = c[d] < lo ? lo : (c[d] > hi ? hi : c[d]);
+        }
+    };
+    for (int l = tid; l < NL; l += kBlock) {
+        const int e[3] = {l % E0, (l / E0) % E1, l / (E0 * E1)};
+        int c[3];
+        clamp_pos(e, B, c);
+        const int id = lin(G, c);
+        sVb[l] = ct_vbar<REC, MET, A, B>(G, args, id);
+        sQa[l] = ldb(sf.p[A], (unsigned)id << 3);
+    }
+    for (int l = tid; l < NLA; l += kBlock) {
+        const int e[3] = {l % F0, (l / F0) % F1, l / (F0 * F1)};
+        int c[3];
+        clamp_pos(e, A, c);
+        sVa[l] = ct_vbar<REC, MET, B, A>(G, args, lin(G, c));
+    }
+    __syncthreads();
+
+    const int t[3] = {tid % T0, (tid / T0) % T1, tid / (T0 * T1)};
+    int c[3] = {org[0] + t[0], org[1] + t[1], org[2] + t[2]};
+    if (c[0] >= R.lo[0] + R.cnt[0] || c[1] >= R.lo[1] + R.cnt[1] || c[2] >= R.lo[2] + R.cnt[2]) return;
+    const int r0 = t[0] + (B == 0 ? HB : 0) + E0 * (t[1] + (B == 1 ? HB : 0) + E1 * (t[2] + (B == 2 ? HB : 0)));
+    const int r1 = t[0] + (A == 0 ? HB : 0) + F0 * (t[1] + (A == 1 ? HB : 0) + F1 * (t[2] + (A == 2 ? HB : 0)));
+    double vbL, vbR, qaL, qaR, vaL, vaR, qbL, qbR;
+    if (actB) {
+        double w[6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sVb[r0 + (m - 3) * SB];
+        recon_face<REC>(w, vbL, vbR);
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sQa[r0 + (m - 3) * SB];
+        recon_face<REC>(w, qaL, qaR);
+    } else {
+        vbL = vbR = sVb[r0];
+        qaL = qaR = sQa[r0];
+    }
+    if (actA) {
+        double w[6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sVa[r1 + (m - 3) * SA];
+        recon_face<REC>(w, vaL, vaR);
+    } else {
+        vaL = vaR = sVa[r1];
+    }
+    const int id = lin(G, c);
+    const unsigned o = (unsigned)id << 3;
+    if (actA) {
+        recon_at<REC>(sf.p[B], id, G.st[A], qbL, qbR);
+    } else {
+        qbL = qbR = ldb(sf.p[B], o);
+    }
+    double ca = 1.0, cb = 1.0;
+    if (MET) {
+        unsigned sa = actA ? ((unsigned)G.st[A] << 3) : 0u, sbb = actB ? ((unsigned)G.st[B] << 3) : 0u;
+        double al0, ps0, al1, ps1;
+        face_metric<MET>(G, met, o - sbb, A, al0, ps0);
+        face_metric<MET>(G, met, o, A, al1, ps1);
+        ca = fmax(al0 * frcp(ps0 * ps0), al1 * frcp(ps1 * ps1));
+        face_metric<MET>(G, met, o - sa, B, al0, ps0);
+        face_metric<MET>(G, met, o, B, al1, ps1);
+        cb = fmax(al0 * frcp(ps0 * ps0), al1 * frcp(ps1 * ps1));
+    }
+    const double t1 = 0.5 * (vaR * qbR + vaL * qbL) - 0.5 * ca * (qbR - qbL);
+    const double t2 = 0.5 * (vbR * qaR + vbL * qaL) - 0.5 * cb * (qaR - qaL);
+    stb(args.EM, o, t2 - t1);
+}
+
 template <int REC, int MET, int K>
 __device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
 {
@@ -507,17 +642,19 @@ __device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
     }
     stb(args.EM, o, ae * 0.25 * (ELL + ELR + ERL + ERR) + 0.5 * ca * (qbR - qbL) - 0.5 * cb * (qaR - qaL));
 }
-template <int REC, int MET, int K>
+template <int REC, int MET, int K, bool IDEAL>
 __global__ void __launch_bounds__(kBlock) k_ct(CtArgs a)
 {
-    ct_body<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
+    if constexpr (IDEAL) ct_ideal_body<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
+    else ct_body<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
 }
-template <int REC, int MET, int K>
+template <int REC, int MET, int K, bool IDEAL>
 __global__ void __launch_bounds__(kBlock) kb_ct(const CtArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
 {
     unsigned lb;
     const CtArgs &a = aa[batch_locate<true>(start, n, lb)];
-    ct_body<REC, MET, K>(a, blk_of(lb, a.gd));
+    if constexpr (IDEAL) ct_ideal_body<REC, MET, K>(a, blk_of(lb, a.gd));
+    else ct_body<REC, MET, K>(a, blk_of(lb, a.gd));
 }
 
 // ---------------------------------------------------------------------------

@@ -35,7 +35,7 @@ class gr_grid(ctypes.Structure):
                 ("rho_atm", ctypes.c_double), ("p_atm", ctypes.c_double), ("metric", ctypes.c_int),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int), ("xi", ctypes.c_double),
                 ("atm_factor", ctypes.c_double), ("frozen_matter", ctypes.c_int), ("glm", ctypes.c_int),
-                ("kappa_E", ctypes.c_double), ("kappa_B", ctypes.c_double)]
+                ("kappa_E", ctypes.c_double), ("kappa_B", ctypes.c_double), ("uct", ctypes.c_int)]
 
 
 class gr_state(ctypes.Structure):
@@ -264,6 +264,7 @@ def grid_of(s) -> gr_grid:
     g.glm = s.glm
     g.kappa_E = s.kappa_E
     g.kappa_B = s.kappa_B
+    g.uct = s.uct
     return g
 
 

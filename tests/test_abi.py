@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     L = grmhd.lib()
     for name in declared_symbols():
         assert hasattr(L, name), name
-    assert grmhd.gr_abi_version() == 3
+    assert grmhd.gr_abi_version() == 4
 
 
 def test_validation_rejects_bad_grids():
@@ -54,7 +54,15 @@ def test_validation_rejects_bad_grids():
     g2.xi = 0.1
     assert grmhd.gr_validate(g2) == grmhd.GR_EUNSUPPORTED  # GLM with the dynamo term
     g2.xi = 0.0
+    g2.uct = 1
+    assert grmhd.gr_validate(g2) == grmhd.GR_EUNSUPPORTED  # GLM has no edge EMF
+    g2.uct = 0
     g2.glm = 2
+    assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
+    g2 = grmhd.grid_of(s)
+    g2.uct = 1
+    assert grmhd.gr_validate(g2) == 0  # ideal-MHD edge EMF supported
+    g2.uct = 2
     assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
     g2 = grmhd.grid_of(s)
     g2.bc[0][0] = W.PERIODIC  # periodic on one side only

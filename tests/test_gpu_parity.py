@@ -88,6 +88,14 @@ CASES = {
     "star_13x11x9_ragged": lambda: _ragged_star(),
     "dynamo_k1_frozen_xi0.5": lambda: W.steady_dynamo(64, k=1),
     "blast_48_ppm_ssp3_xi0.05": lambda: _with(W.blast_wave(48, eta=1e-2), xi=0.05),
+    # ideal-MHD edge EMF (App. A)
+    "shock_tube_400_minmod_ssp2_uct_ideal": lambda: _with(W.shock_tube(400), uct=1),
+    "blast_48_ppm_ssp3_stiff_uct_ideal": lambda: _with(W.blast_wave(48, eta=1e-6), uct=1),
+    "blast_48_ppm_ssp3_eta1e-2_uct_ideal": lambda: _with(W.blast_wave(48, eta=1e-2), uct=1),
+    "blast_37x23_mc_ssp2_uct_ideal": lambda: _with(_ragged_blast(), uct=1),
+    "loop_periodic_40x20_uct_ideal": lambda: _with(W.loop_advection(40, 20), uct=1),
+    "star_24_cowling_uct_ideal": lambda: _with(W.tov_star(24), uct=1),
+    "star_13x11x9_ragged_uct_ideal": lambda: _with(_ragged_star(), uct=1),
 }
 
 
@@ -155,7 +163,8 @@ def test_one_step_parity(name):
 
 
 @pytest.mark.parametrize("name", ["shock_tube_400_minmod_ssp2", "blast_48_ppm_ssp3_eta1e-2", "star_24_cowling",
-                                  "dynamo_k1_frozen_xi0.5"])
+                                  "dynamo_k1_frozen_xi0.5", "blast_48_ppm_ssp3_eta1e-2_uct_ideal",
+                                  "star_24_cowling_uct_ideal"])
 def test_hundred_steps_parity(name):
     _torch()
     say("case %s: 100 steps" % name)
