@@ -346,11 +346,14 @@ gr_status check_state(const gr_grid *g, const gr_state *st)
 // Kernel variants: the template instance of each tiled kernel a run uses.
 // The x/y phase tile and the z-phase tile of the cell pass are the tunables
 // (the batch autotuner picks them per class of runs).
-enum XyTile { XY_32x8 = 0, XY_64x4, XY_16x16, XY_256x1, XY_128x1, XY_64x1, XY_COUNT };
+// 32x7 leaves one wavefront's worth of lanes without a cell so that every
+// face of the tile has its own thread (one HLL evaluation per thread, no
+// second partial round); the z-phase tiles of the cell pass are TX x 1 x TZ.
+enum XyTile { XY_32x7 = 0, XY_32x8, XY_64x4, XY_16x16, XY_256x1, XY_128x1, XY_64x1, XY_COUNT };
 enum CzTile { CZ_16x16 = 0, CZ_32x8, CZ_COUNT };
-const int kXyTX[XY_COUNT] = {32, 64, 16, 256, 128, 64}, kXyTY[XY_COUNT] = {8, 4, 16, 1, 1, 1};
+const int kXyTX[XY_COUNT] = {32, 32, 64, 16, 256, 128, 64}, kXyTY[XY_COUNT] = {7, 8, 4, 16, 1, 1, 1};
 const int kCzTX[CZ_COUNT] = {16, 32}, kCzTZ[CZ_COUNT] = {16, 8};
-const char *kXyName[XY_COUNT] = {"32x8", "64x4", "16x16", "256x1", "128x1", "64x1"};
+const char *kXyName[XY_COUNT] = {"32x7", "32x8", "64x4", "16x16", "256x1", "128x1", "64x1"};
 const char *kCzName[CZ_COUNT] = {"16x16", "32x8"};
 
 struct Variant {
@@ -373,7 +376,7 @@ Variant default_variant(const gr_grid *g)
     Variant V;
     V.rec = g->recon;
     V.met = g->metric ? 1 : 0;
-    V.xy = g->ndim >= 2 ? XY_32x8 : XY_256x1;
+    V.xy = g->ndim >= 2 ? (g->glm ? XY_32x8 : XY_32x7) : XY_256x1;
     V.cz = CZ_16x16;
     V.xi = g->xi != 0.0 ? 1 : 0;
     V.glm = g->glm ? 1 : 0;
@@ -401,6 +404,7 @@ void with_xy(int t, F &&f)
     case XY_32x8: f(IC<32>{}, IC<8>{}); break;
     case XY_64x4: f(IC<64>{}, IC<4>{}); break;
     case XY_16x16: f(IC<16>{}, IC<16>{}); break;
+    case XY_32x7: f(IC<32>{}, IC<7>{}); break;
     case XY_256x1: f(IC<256>{}, IC<1>{}); break;
     case XY_128x1: f(IC<128>{}, IC<1>{}); break;
     default: f(IC<64>{}, IC<1>{}); break;
@@ -431,7 +435,8 @@ const int kCtOrder[3] = {2, 0, 1};
 // Everything one pass of one run launches, in launch order: ghost fill,
 // x/y phases, the three EMF components, the face update, the cell pass.
 struct PassPlan {
-    bool ghost = false, xy = false, face = false, swz = false;
+    bool ghost = false, xy = false, face = false;
+    bool swz = false;  // cell pass with the z phase
     bool ct[3] = {false, false, false};
     GhostArgs gh;
     XyArgs xya;
@@ -667,7 +672,7 @@ void launch_xy(const Variant &V, const XyArgs &a, hipStream_t s)
                 if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value, gl>())
                     hipLaunchKernelGGL((k_xy<decltype(R)::value, decltype(M)::value, decltype(TX)::value,
                                              decltype(TY)::value, gl>),
-                                       d3(a.gd), dim3(decltype(TX)::value * decltype(TY)::value), 0, s, a);
+                                       d3(a.gd), dim3(tile_threads(decltype(TX)::value * decltype(TY)::value)), 0, s, a);
             });
         });
     });
@@ -686,26 +691,26 @@ void launch_ct(const Variant &V, int K, const CtArgs &a, hipStream_t s)
 }
 // cell-pass instances: the dynamo and GLM are not combined (validated), GLM
 // uses the default z-phase tile
-template <bool XI, bool GLM, int TX>
+template <bool XI, bool GLM, int TX, int TZ>
 constexpr bool cell_compiled()
 {
-    return !(XI && GLM) && !(GLM && TX != 16 && TX != 1);
+    return !(XI && GLM) && !(GLM && !(TX == 16 && TZ == 16) && TX != 1);
 }
-void launch_cell(const Variant &V, bool swz, const CellArgs &a, hipStream_t s)
+void launch_cell(const Variant &V, int swz, const CellArgs &a, hipStream_t s)
 {
     with_rm(V.rec, V.met, [&](auto R, auto M) {
         constexpr int r = decltype(R)::value, m = decltype(M)::value;
         auto go = [&](auto X, auto GL) {
             constexpr bool x = decltype(X)::value != 0, gl = decltype(GL)::value != 0;
             if (!swz) {
-                if constexpr (cell_compiled<x, gl, 1>())
+                if constexpr (cell_compiled<x, gl, 1, 1>())
                     hipLaunchKernelGGL((k_cell_update<r, m, 0, 1, 1, x, gl>), d3(a.gd), dim3(kBlock), 0, s, a);
                 return;
             }
             with_cz(V.cz, [&](auto TX, auto TZ) {
-                if constexpr (cell_compiled<x, gl, decltype(TX)::value>())
-                    hipLaunchKernelGGL((k_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value, x, gl>),
-                                       d3(a.gd), dim3(kBlock), 0, s, a);
+                constexpr int tx = decltype(TX)::value, tz = decltype(TZ)::value;
+                if constexpr (cell_compiled<x, gl, tx, tz>())
+                    hipLaunchKernelGGL((k_cell_update<r, m, 1, tx, tz, x, gl>), d3(a.gd), dim3(kBlock), 0, s, a);
             });
         };
         if (V.glm) go(IC<0>{}, IC<1>{});
@@ -974,7 +979,7 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
                     if constexpr (xy_compiled<decltype(M)::value, decltype(TX)::value, decltype(TY)::value, gl>())
                         hipLaunchKernelGGL((kb_xy<decltype(R)::value, decltype(M)::value, decltype(TX)::value,
                                                   decltype(TY)::value, gl>),
-                                           grid, dim3(decltype(TX)::value * decltype(TY)::value), 0, s,
+                                           grid, dim3(tile_threads(decltype(TX)::value * decltype(TY)::value)), 0, s,
                                            (const XyArgs *)L.args, L.start, L.n);
                 });
             });
@@ -1002,15 +1007,16 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
             auto go = [&](auto X, auto GLx) {
                 constexpr bool x = decltype(X)::value != 0, gl = decltype(GLx)::value != 0;
                 if (!L.swz) {
-                    if constexpr (cell_compiled<x, gl, 1>())
+                    if constexpr (cell_compiled<x, gl, 1, 1>())
                         hipLaunchKernelGGL((kb_cell_update<r, m, 0, 1, 1, x, gl>), grid, dim3(kBlock), 0, s, a,
                                            L.start, L.n);
                     return;
                 }
                 with_cz(L.V.cz, [&](auto TX, auto TZ) {
-                    if constexpr (cell_compiled<x, gl, decltype(TX)::value>())
-                        hipLaunchKernelGGL((kb_cell_update<r, m, 1, decltype(TX)::value, decltype(TZ)::value, x, gl>),
-                                           grid, dim3(kBlock), 0, s, a, L.start, L.n);
+                    constexpr int tx = decltype(TX)::value, tz = decltype(TZ)::value;
+                    if constexpr (cell_compiled<x, gl, tx, tz>())
+                        hipLaunchKernelGGL((kb_cell_update<r, m, 1, tx, tz, x, gl>), grid, dim3(kBlock), 0, s, a,
+                                           L.start, L.n);
                 });
             };
             if (L.V.glm) go(IC<0>{}, IC<1>{});

@@ -187,9 +187,13 @@ __device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const C
 // through the same LDS and each thread returns minus the flux difference of
 // its cell divided by dx_D.  Coordinates are clamped into the padded array;
 // results for points beyond the interior are computed but never stored.
+// threads of a block that owns a tile of n cells: whole wavefronts
+constexpr int tile_threads(int n) { return (n + 63) / 64 * 64; }
+
 template <int D, int T0, int T1, int T2, bool GLM = false>
 struct PhaseDims {
-    static constexpr int NT = T0 * T1 * T2;
+    static constexpr int NC = T0 * T1 * T2;  // cells of the tile
+    static constexpr int NT = tile_threads(NC);
     static constexpr int H = 3;
     static constexpr int E0 = T0 + (D == 0 ? 2 * H : 0), E1 = T1 + (D == 1 ? 2 * H : 0),
                          E2 = T2 + (D == 2 ? 2 * H : 0);
@@ -251,11 +255,12 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
     }
     __syncthreads();
 
-    double Fr[2][NFL];
+    constexpr int NFR = (NF + NT - 1) / NT;  // faces per thread (1 or 2)
+    double Fr[NFR][NFL];
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < NFR; k++) {
         const int f = tid + k * NT;
-        if (k == 1 && f >= NF) break;
+        if (f >= NF) break;
         int e[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
         const int r0 = (e[0] + (D == 0 ? H : 0)) + E0 * ((e[1] + (D == 1 ? H : 0)) + E1 * (e[2] + (D == 2 ? H : 0)));
         double sL[NV], sR[NV];
@@ -284,16 +289,21 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
     __syncthreads();
     double(*fl)[NF] = reinterpret_cast<double(*)[NF]>(lds);
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < NFR; k++) {
         const int f = tid + k * NT;
-        if (k == 1 && f >= NF) break;
+        if (f >= NF) break;
 #pragma unroll
         for (int v = 0; v < NFL; v++) fl[v][f] = Fr[k][v];
     }
     __syncthreads();
-    const int f0 = (tid % T0) + F0 * (((tid / T0) % T1) + F1 * (tid / (T0 * T1)));
+    if (tid < PD::NC) {
+        const int f0 = (tid % T0) + F0 * (((tid / T0) % T1) + F1 * (tid / (T0 * T1)));
 #pragma unroll
-    for (int v = 0; v < NFL; v++) Ld[v] = -(fl[v][f0 + PD::FS] - fl[v][f0]) * G.idx[D];
+        for (int v = 0; v < NFL; v++) Ld[v] = -(fl[v][f0 + PD::FS] - fl[v][f0]) * G.idx[D];
+    } else {
+#pragma unroll
+        for (int v = 0; v < NFL; v++) Ld[v] = 0.0;  // threads beyond the tile own no cell
+    }
     __syncthreads();  // the buffer is free for the next phase
 }
 
@@ -328,6 +338,7 @@ __device__ __forceinline__ void xy_body(const XyArgs &a, Blk blk)
 #pragma unroll
         for (int v = 0; v < NFL; v++) L[v] += Ly[v];
     }
+    if ((int)threadIdx.x >= TX * TY) return;  // beyond the tile
     const int c[3] = {org[0] + (int)threadIdx.x % TX, org[1] + (int)threadIdx.x / TX, org[2]};
     if (c[0] >= G.g[0] + G.n[0] || c[1] >= G.g[1] + G.n[1]) return;
     const unsigned o = (unsigned)lin(G, c) << 3;
@@ -335,12 +346,12 @@ __device__ __forceinline__ void xy_body(const XyArgs &a, Blk blk)
     for (int v = 0; v < NFL; v++) stb(a.Lxy.p[v], o, L[v]);
 }
 template <int REC, int MET, int TX, int TY, bool GLM>
-__global__ void __launch_bounds__(TX *TY) k_xy(XyArgs a)
+__global__ void __launch_bounds__(tile_threads(TX *TY)) k_xy(XyArgs a)
 {
     xy_body<REC, MET, TX, TY, GLM>(a, blk_of(hw_linear<true>(), a.gd));
 }
 template <int REC, int MET, int TX, int TY, bool GLM>
-__global__ void __launch_bounds__(TX *TY) kb_xy(const XyArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
+__global__ void __launch_bounds__(tile_threads(TX *TY)) kb_xy(const XyArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
 {
     unsigned lb;
     const XyArgs &a = aa[batch_locate<true>(start, n, lb)];
@@ -367,12 +378,13 @@ __device__ __forceinline__ void face_metric(const Geo &G, const CPtr<2> &met, un
 }
 
 // Upwind constrained-transport EMF hat-E_k on the k-edges (Sec 3.2), (k, a, b)
-// cyclic.  One block owns a tile of edges.  Step 1 forms, for every a-face the
-// tile needs (its edges' a-index, b widened by the reconstruction halo), the
-// left/right states of the covariant E_k = psi^4 E^k reconstructed along a and
-// the normal face field q_B^a; they go to LDS.  Step 2 reconstructs those
-// along b to the edge (the LL, LR, RL, RR states), reconstructs q_B^b along a,
-// and combines them with the metric-only speeds (c+ = c-).
+// cyclic.  One block owns a tile of edges (one edge per thread).  The
+// left/right states of the covariant E_k = psi^4 E^k reconstructed along a to
+// the a-faces (b widened by the reconstruction halo) are formed first and go
+// to LDS; then each edge reconstructs them along b (the LL, LR, RL, RR
+// states), q_B^a along b and q_B^b along a, and combines them with the
+// metric-only speeds (c+ = c-).  ct_body stages every input in LDS;
+// ct_body_direct (x-edges) reads the cell values from memory.
 template <int K>
 struct CtTile;
 template <>
@@ -532,8 +544,14 @@ __device__ __forceinline__ void ct_ideal_body(const CtArgs &args, Blk blk)
     stb(args.EM, o, t2 - t1);
 }
 
+// Upwind EMF reading its cell values directly (used for the x-edges, whose
+// narrow transverse tile would make the staged boxes mostly halo): step 1
+// forms, for every a-face the tile needs (b widened by the reconstruction
+// halo), the left/right states of psi^4 E_K reconstructed along a and q_B^a
+// in LDS; step 2 reconstructs them along b, q_B^b along a from memory, and
+// combines them with the metric-only speeds.
 template <int REC, int MET, int K>
-__device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
+__device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
 {
     const Geo &G = args.G;
     const Region &R = args.R;
@@ -642,10 +660,198 @@ __device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
     }
     stb(args.EM, o, ae * 0.25 * (ELL + ELR + ERL + ERR) + 0.5 * ca * (qbR - qbL) - 0.5 * cb * (qaR - qaL));
 }
+// An LDS box of the EMF tile of edge direction K: a in [OA, OA + NA), b in
+// [OB, OB + NB), k in [0, T_k) relative to the tile origin, stored x fastest
+// (consecutive lanes touch consecutive words when they step along x).
+template <int K, int NA, int NB, int OA, int OB>
+struct CtBox {
+    static constexpr int A = (K + 1) % 3, B = (K + 2) % 3;
+    static constexpr int TK = CtTile<K>::T[K];
+    static constexpr int X[3] = {A == 0 ? NA : (B == 0 ? NB : TK), A == 1 ? NA : (B == 1 ? NB : TK),
+                                 A == 2 ? NA : (B == 2 ? NB : TK)};
+    static constexpr int O[3] = {A == 0 ? OA : (B == 0 ? OB : 0), A == 1 ? OA : (B == 1 ? OB : 0),
+                                 A == 2 ? OA : (B == 2 ? OB : 0)};
+    static constexpr int S[3] = {1, X[0], X[0] * X[1]};
+    static constexpr int N = NA * NB * TK;
+    // index of the point with tile-local coordinates t (x, y, z)
+    __device__ static int at(int t0, int t1, int t2)
+    {
+        return (t0 - O[0]) + S[1] * (t1 - O[1]) + S[2] * (t2 - O[2]);
+    }
+};
+
+// stage one cell-sized field over a box (coordinates clamped into the padded
+// array; clamped points only feed results that are never stored); all loads
+// of a thread are issued before its LDS stores
+template <class BX>
+__device__ __forceinline__ void ct_stage(const Geo &G, const double *__restrict__ f, const int org[3], double *dst)
+{
+    constexpr int NR = (BX::N + kBlock - 1) / kBlock;
+    double v[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const int l = (int)threadIdx.x + r * kBlock;
+        if (l < BX::N) {
+            int c[3] = {org[0] + BX::O[0] + l % BX::X[0], org[1] + BX::O[1] + (l / BX::X[0]) % BX::X[1],
+                        org[2] + BX::O[2] + l / (BX::X[0] * BX::X[1])};
+#pragma unroll
+            for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
+            v[r] = ldb(f, (unsigned)lin(G, c) << 3);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const int l = (int)threadIdx.x + r * kBlock;
+        if (l < BX::N) dst[l] = v[r];
+    }
+}
+
+// Upwind EMF with every input staged in LDS by coalesced loads: E_K over the
+// tile widened by the reconstruction halo in a and b, psi and alpha for the
+// face and edge metric factors, q_B^a of the a-faces widened along b and q_B^b
+// of the b-faces widened along a.  Step 1 reconstructs psi^4 E_K along a to
+// the a-faces of the b-widened rows; step 2 reconstructs those along b (LL,
+// LR, RL, RR), q_B^a along b and q_B^b along a, and combines them with the
+// metric-only speeds.
+template <int REC, int MET, int K>
+__device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
+{
+    const Geo &G = args.G;
+    const Region &R = args.R;
+    constexpr int A = (K + 1) % 3, B = (K + 2) % 3;
+    constexpr int TA = CtTile<K>::T[A], TB = CtTile<K>::T[B];
+    static_assert(CtTile<K>::T[0] * CtTile<K>::T[1] * CtTile<K>::T[2] == kBlock, "one edge per thread");
+    using BE = CtBox<K, TA + 5, TB + 5, -3, -3>;  // E_K: a, b in [-3, T + 2)
+    using BP = CtBox<K, TA + 1, TB + 5, -1, -3>;  // psi: a in [-1, T_a), b in [-3, T_b + 2)
+    using BA = CtBox<K, TA + 1, TB + 1, -1, -1>;  // alpha: a in [-1, T_a), b in [-1, T_b)
+    using BQa = CtBox<K, TA, TB + 5, 0, -3>;      // q_B^a and the a-face states of psi^4 E_K
+    using BQb = CtBox<K, TA + 5, TB, -3, 0>;      // q_B^b
+    __shared__ double sE[BE::N], sP[MET ? BP::N : 1], sAl[MET ? BA::N : 1], sQa[BQa::N], sQb[BQb::N];
+    __shared__ double sEL[BQa::N], sER[BQa::N];
+
+    const int org[3] = {R.lo[0] + (int)blk.x * CtTile<K>::T[0], R.lo[1] + (int)blk.y * CtTile<K>::T[1],
+                        R.lo[2] + (int)blk.z * CtTile<K>::T[2]};
+    const bool actA = G.act[A], actB = G.act[B];
+    ct_stage<BE>(G, args.Ek, org, sE);
+    ct_stage<BQa>(G, args.sf.p[A], org, sQa);
+    ct_stage<BQb>(G, args.sf.p[B], org, sQb);
+    if (MET) {
+        ct_stage<BP>(G, args.met.p[1], org, sP);
+        ct_stage<BA>(G, args.met.p[0], org, sAl);
+    }
+    __syncthreads();
+
+    // ---- step 1: a-face states of psi^4 E_K on the rows b in [-3, T_b + 2)
+    for (int l = (int)threadIdx.x; l < BQa::N; l += kBlock) {
+        int e[3] = {BQa::O[0] + l % BQa::X[0], BQa::O[1] + (l / BQa::X[0]) % BQa::X[1],
+                    BQa::O[2] + l / (BQa::X[0] * BQa::X[1])};  // tile-local face position
+        const int e0 = BE::at(e[0], e[1], e[2]);
+        double p4 = 1.0;
+        if (MET) {
+            const int q = BP::at(e[0], e[1], e[2]);  // psi of the cell above the face; below: - S[A]
+            const double ps = actA ? 0.5 * (sP[q - BP::S[A]] + sP[q]) : sP[q];
+            const double p2 = ps * ps;
+            p4 = p2 * p2;
+        }
+        double L, Rv;
+        if (actA) {
+            double w[6];
+#pragma unroll
+            for (int m = 0; m < 6; m++) w[m] = sE[e0 + (m - 3) * BE::S[A]];
+            recon_face<REC>(w, L, Rv);
+        } else {
+            L = Rv = sE[e0];
+        }
+        sEL[l] = p4 * L;
+        sER[l] = p4 * Rv;
+    }
+    __syncthreads();
+
+    // ---- step 2: this thread's edge
+    const int t[3] = {(int)threadIdx.x % CtTile<K>::T[0], ((int)threadIdx.x / CtTile<K>::T[0]) % CtTile<K>::T[1],
+                      (int)threadIdx.x / (CtTile<K>::T[0] * CtTile<K>::T[1])};
+    int c[3] = {org[0] + t[0], org[1] + t[1], org[2] + t[2]};
+    if (c[0] >= R.lo[0] + R.cnt[0] || c[1] >= R.lo[1] + R.cnt[1] || c[2] >= R.lo[2] + R.cnt[2]) return;
+    double ELL, ELR, ERL, ERR, qaL, qaR, qbL, qbR;
+    const int r0 = BQa::at(t[0], t[1], t[2]);  // a-face row of the edge (b - 1/2 lies below it)
+    if (actB) {
+        double w[6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sEL[r0 + (m - 3) * BQa::S[B]];
+        recon_face<REC>(w, ELL, ELR);
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sER[r0 + (m - 3) * BQa::S[B]];
+        recon_face<REC>(w, ERL, ERR);
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sQa[r0 + (m - 3) * BQa::S[B]];
+        recon_face<REC>(w, qaL, qaR);
+    } else {
+        ELL = ELR = sEL[r0];
+        ERL = ERR = sER[r0];
+        qaL = qaR = sQa[r0];
+    }
+    const int r1 = BQb::at(t[0], t[1], t[2]);  // b-face of the edge
+    if (actA) {
+        double w[6];
+#pragma unroll
+        for (int m = 0; m < 6; m++) w[m] = sQb[r1 + (m - 3) * BQb::S[A]];
+        recon_face<REC>(w, qbL, qbR);
+    } else {
+        qbL = qbR = sQb[r1];
+    }
+    double ca = 1.0, cb = 1.0, ae = 1.0;
+    if (MET) {
+        // alpha and psi of the cells (a - 1 .. a, b - 1 .. b) around the edge
+        const int q11 = BA::at(t[0], t[1], t[2]), p11 = BP::at(t[0], t[1], t[2]);
+        const double a11 = sAl[q11], a01 = sAl[q11 - BA::S[A]], a10 = sAl[q11 - BA::S[B]],
+                     a00 = sAl[q11 - BA::S[A] - BA::S[B]];
+        const double p_11 = sP[p11], p_01 = sP[p11 - BP::S[A]], p_10 = sP[p11 - BP::S[B]],
+                     p_00 = sP[p11 - BP::S[A] - BP::S[B]];
+        // a-face speeds at rows b - 1 and b, b-face speeds at columns a - 1 and a
+        double al0, ps0, al1, ps1;
+        al0 = actA ? 0.5 * (a00 + a10) : a10;
+        ps0 = actA ? 0.5 * (p_00 + p_10) : p_10;
+        al1 = actA ? 0.5 * (a01 + a11) : a11;
+        ps1 = actA ? 0.5 * (p_01 + p_11) : p_11;
+        if (!actB) {
+            al0 = al1;
+            ps0 = ps1;
+        }
+        ca = fmax(al0 * frcp(ps0 * ps0), al1 * frcp(ps1 * ps1));
+        al0 = actB ? 0.5 * (a00 + a01) : a01;
+        ps0 = actB ? 0.5 * (p_00 + p_01) : p_01;
+        al1 = actB ? 0.5 * (a10 + a11) : a11;
+        ps1 = actB ? 0.5 * (p_10 + p_11) : p_11;
+        if (!actA) {
+            al0 = al1;
+            ps0 = ps1;
+        }
+        cb = fmax(al0 * frcp(ps0 * ps0), al1 * frcp(ps1 * ps1));
+        double sm = a11;
+        int na = 1;
+        if (actA) {
+            sm += a01;
+            na++;
+        }
+        if (actB) {
+            sm += a10;
+            na++;
+        }
+        if (actA && actB) {
+            sm += a00;
+            na++;
+        }
+        ae = sm / na;
+    }
+    const unsigned o = (unsigned)lin(G, c) << 3;
+    stb(args.EM, o, ae * 0.25 * (ELL + ELR + ERL + ERR) + 0.5 * ca * (qbR - qbL) - 0.5 * cb * (qaR - qaL));
+}
+
 template <int REC, int MET, int K, bool IDEAL>
 __global__ void __launch_bounds__(kBlock) k_ct(CtArgs a)
 {
     if constexpr (IDEAL) ct_ideal_body<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
+    else if constexpr (K == 0) ct_body_direct<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
     else ct_body<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
 }
 template <int REC, int MET, int K, bool IDEAL>
@@ -654,6 +860,7 @@ __global__ void __launch_bounds__(kBlock) kb_ct(const CtArgs *__restrict__ aa, c
     unsigned lb;
     const CtArgs &a = aa[batch_locate<true>(start, n, lb)];
     if constexpr (IDEAL) ct_ideal_body<REC, MET, K>(a, blk_of(lb, a.gd));
+    else if constexpr (K == 0) ct_body_direct<REC, MET, K>(a, blk_of(lb, a.gd));
     else ct_body<REC, MET, K>(a, blk_of(lb, a.gd));
 }
 
@@ -777,8 +984,8 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     constexpr int NQ = NVar<GLM>::NF;
     int c[3];
     double Lz[NQ];
-    if (SWZ) {
-        __shared__ double lds[SWZ ? PhaseDims<2, TX, 1, TZ, GLM>::LDS : 1];
+    if constexpr (SWZ == 1) {
+        __shared__ double lds[PhaseDims<2, TX, 1, TZ, GLM>::LDS];
         const int org[3] = {R.lo[0] + (int)blk.x * TX, R.lo[1] + (int)blk.y, R.lo[2] + (int)blk.z * TZ};
         CPtr<10> sp;
         CPtr<3> sf;
@@ -789,7 +996,9 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         for (int d = 0; d < 3; d++) sf.p[d] = io.sfm[d];
         met.p[0] = io.met[0];
         met.p[1] = io.met[1];
+        static_assert(PhaseDims<2, TX, 1, TZ, GLM>::NT == kBlock, "z-phase tile of one block");
         sweep_phase<REC, MET, 2, TX, 1, TZ, GLM>(G, P, sp, sf, met, org, lds, Lz);
+        if ((int)threadIdx.x >= TX * TZ) return;  // beyond the tile
         c[0] = org[0] + (int)threadIdx.x % TX;
         c[1] = org[1];
         c[2] = org[2] + (int)threadIdx.x / TX;
