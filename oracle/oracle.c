@@ -21,11 +21,19 @@
  *             velocity residual (eq. f_u_for_e), Jacobian, Newton iteration
  *   Sec 2.5   maximum-diffusivity characteristic speeds
  *   Sec 2.6   conservative-to-primitive recovery with E and B given
+ *   Sec 3.1   GLM hyperbolic divergence cleaning (cell-centred B, Psi, Phi)
  *   Sec 3.2   staggered constrained transport (eq. B_surface, eq. ct) and the
  *             HLL-based upwind EMF, steps (i)-(vii)
+ *   App. A    the ideal-MHD form of the upwind EMF (transport velocities)
  *   Sec 4     face fields from an edge vector potential
+ *   Sec 5.7   mean-field dynamo (xi != 0) in the implicit update
  * Readings of places where the paper is silent or garbled are stated next to
  * the code that takes them.
+ *
+ * Parity unpinned (no closed form or printed value fixes them; they are
+ * checked only through the invariants of the test-suite and agreement with
+ * the HIP library): the PPM variant details (the paper names PPM only), the
+ * atmosphere / failure rule, and the conductivity clamp of eq. sigma_D.
  */
 #include <math.h>
 #include <stdlib.h>
