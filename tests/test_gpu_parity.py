@@ -88,6 +88,14 @@ CASES = {
     "star_13x11x9_ragged": lambda: _ragged_star(),
     "dynamo_k1_frozen_xi0.5": lambda: W.steady_dynamo(64, k=1),
     "blast_48_ppm_ssp3_xi0.05": lambda: _with(W.blast_wave(48, eta=1e-2), xi=0.05),
+    # degenerate and minimal shapes: one-cell-thick active directions, periodic
+    # grids as small as the ghost width, fixed boundaries
+    "box_3d_12x9x1_outflow_mc": lambda: _smooth_box(3, (12, 9, 1), W.OUTFLOW),
+    "box_3d_1x10x8_outflow_ppm_ssp3": lambda: _smooth_box(3, (1, 10, 8), W.OUTFLOW, W.PPM, W.SSP3),
+    "box_2d_1x16_outflow_mc": lambda: _smooth_box(2, (1, 16, 1), W.OUTFLOW),
+    "box_1d_3_periodic_ppm": lambda: _smooth_box(1, (3, 1, 1), W.PERIODIC, W.PPM),
+    "box_3d_3x3x3_periodic_ppm_ssp3": lambda: _smooth_box(3, (3, 3, 3), W.PERIODIC, W.PPM, W.SSP3),
+    "box_2d_5x4_fixed_minmod": lambda: _smooth_box(2, (5, 4, 1), W.FIXED, W.MINMOD),
     # ideal-MHD edge EMF (App. A)
     "shock_tube_400_minmod_ssp2_uct_ideal": lambda: _with(W.shock_tube(400), uct=1),
     "blast_48_ppm_ssp3_stiff_uct_ideal": lambda: _with(W.blast_wave(48, eta=1e-6), uct=1),
@@ -97,6 +105,31 @@ CASES = {
     "star_24_cowling_uct_ideal": lambda: _with(W.tov_star(24), uct=1),
     "star_13x11x9_ragged_uct_ideal": lambda: _with(_ragged_star(), uct=1),
 }
+
+
+def _smooth_box(ndim, n, bc, recon=W.MC, imex=W.SSP2):
+    """degenerate and minimal shapes: a smooth bump of density and pressure,
+    a swirl, a uniform field with E = -v x B, on [-1, 1]^ndim"""
+    ng = 3 if recon == W.PPM else 2
+    s = W._blank(W.Setup("box", ndim, n, ng, (-1, -1, -1), (1, 1, 1), W._bc(ndim, bc), 5.0 / 3.0, recon, imex,
+                         eta=1e-2))
+    X, Y, Z = s.mesh()
+    r2 = sum(a * a for a, d in zip((X, Y, Z), range(3)) if s.active(d))
+    g = np.exp(-2.0 * r2)
+    s.prim[0] = 1.0 + 0.3 * g
+    s.prim[4] = 0.5 + 0.2 * g
+    v = [0.2 * g * (Y if ndim > 1 else 1.0), -0.15 * g * X, 0.1 * g]
+    Wl = 1.0 / np.sqrt(1.0 - v[0] ** 2 - v[1] ** 2 - v[2] ** 2)
+    B = (0.3, 0.2, 0.1)
+    for i in range(3):
+        s.prim[1 + i] = Wl * v[i]
+    s.E[0] = -(v[1] * B[2] - v[2] * B[1])
+    s.E[1] = -(v[2] * B[0] - v[0] * B[2])
+    s.E[2] = -(v[0] * B[1] - v[1] * B[0])
+    s.face = np.zeros((3,) + s.shape)
+    for i in range(3):
+        s.face[i] = B[i]
+    return s
 
 
 def _with(s, **kw):
