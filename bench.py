@@ -46,18 +46,43 @@ def csrc_digest():
     return hashlib.sha256(b"".join(open(f, "rb").read() for f in files)).hexdigest()[:16]
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken"""
+def profiled_value(pattern, key, kernel):
+    """a per-launch figure of `kernel` from a committed counter summary
+    (profiles/<pattern>), or None when the kernel sources changed since the
+    counters were taken"""
     import glob
     import re
-    for f in glob.glob(os.path.join(ROOT, "profiles", "*hbm_traffic.md")):
+    for f in glob.glob(os.path.join(ROOT, "profiles", pattern)):
         txt = open(f).read()
         m = re.search(r"csrc-sha256-16: ([0-9a-f]+)", txt)
-        t = re.search(r"traffic-bytes-per-launch %s: ([0-9.]+)" % re.escape(kernel), txt)
+        t = re.search(r"%s %s: ([0-9.]+)" % (re.escape(key), re.escape(kernel)), txt)
         if m and t and m.group(1) == csrc_digest():
             return float(t.group(1))
     return None
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"""
+    return profiled_value("*hbm_traffic.md", "traffic-bytes-per-launch", kernel)
+
+
+def profiled_fp64_flop(kernel):
+    """FP64 flops per launch (rocprofv3 SQ_INSTS_VALU_*_F64)"""
+    return profiled_value("*fp64_valu*.md", "fp64-flop-per-launch", kernel)
+
+
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
+
+
+def fp64_rate(kernel, avg_us):
+    """the FP64 VALU side of the roofline: counted flops per launch (from
+    the committed counter summary) over the live average launch time"""
+    fl = profiled_fp64_flop(kernel)
+    if fl is None:
+        return None
+    tf = fl / (avg_us * 1e-6) / 1e12
+    return {"achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+            "flop_per_launch": fl}
 
 
 def kernel_roofline(run, dt, steps, grmhd, torch):
@@ -84,6 +109,7 @@ def kernel_roofline(run, dt, steps, grmhd, torch):
         "bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(name), "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
         "avg_launch_us": round(ms * 1e3 / n, 2), "launches": n, "alg_bytes_per_launch": by / n,
+        "fp64": fp64_rate(name, ms * 1e3 / n),
     }, {k: {"ms_per_step": round(v[0] / steps, 4), "launches_per_step": v[1] / steps,
             "alg_GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)} for k, v in per.items()}
 
