@@ -687,16 +687,29 @@ template <class BX>
 __device__ __forceinline__ void ct_stage(const Geo &G, const double *__restrict__ f, const int org[3], double *dst)
 {
     constexpr int NR = (BX::N + kBlock - 1) / kBlock;
+    constexpr unsigned X0 = BX::X[0], X1 = BX::X[1];
+    const int b[3] = {org[0] + BX::O[0], org[1] + BX::O[1], org[2] + BX::O[2]};
+    // most boxes lie inside the padded array: no clamping, one base offset
+    bool inner = true;
+#pragma unroll
+    for (int d = 0; d < 3; d++) inner = inner && b[d] >= 0 && b[d] + BX::X[d] <= G.N[d];
+    const unsigned base = inner ? (unsigned)lin(G, b) : 0u;
     double v[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        const int l = (int)threadIdx.x + r * kBlock;
-        if (l < BX::N) {
-            int c[3] = {org[0] + BX::O[0] + l % BX::X[0], org[1] + BX::O[1] + (l / BX::X[0]) % BX::X[1],
-                        org[2] + BX::O[2] + l / (BX::X[0] * BX::X[1])};
+        const unsigned l = threadIdx.x + (unsigned)(r * kBlock);
+        if (l < (unsigned)BX::N) {
+            const unsigned e0 = l % X0, q = l / X0, e1 = q % X1, e2 = q / X1;
+            unsigned off;
+            if (inner) {
+                off = base + e0 + e1 * (unsigned)G.st[1] + e2 * (unsigned)G.st[2];
+            } else {
+                int c[3] = {b[0] + (int)e0, b[1] + (int)e1, b[2] + (int)e2};
 #pragma unroll
-            for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
-            v[r] = ldb(f, (unsigned)lin(G, c) << 3);
+                for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
+                off = (unsigned)lin(G, c);
+            }
+            v[r] = ldb(f, off << 3);
         }
     }
 #pragma unroll
@@ -742,9 +755,11 @@ __device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
     __syncthreads();
 
     // ---- step 1: a-face states of psi^4 E_K on the rows b in [-3, T_b + 2)
-    for (int l = (int)threadIdx.x; l < BQa::N; l += kBlock) {
-        int e[3] = {BQa::O[0] + l % BQa::X[0], BQa::O[1] + (l / BQa::X[0]) % BQa::X[1],
-                    BQa::O[2] + l / (BQa::X[0] * BQa::X[1])};  // tile-local face position
+    for (unsigned l = threadIdx.x; l < (unsigned)BQa::N; l += kBlock) {
+        constexpr unsigned Q0 = BQa::X[0], Q1 = BQa::X[1];
+        const unsigned q = l / Q0;
+        int e[3] = {BQa::O[0] + (int)(l % Q0), BQa::O[1] + (int)(q % Q1),
+                    BQa::O[2] + (int)(q / Q1)};  // tile-local face position
         const int e0 = BE::at(e[0], e[1], e[2]);
         double p4 = 1.0;
         if (MET) {
