@@ -260,7 +260,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one MI355X only; runs on more than one GPU are not supported "
-              "(independent runs shard by whole runs, see DESIGN.md)", file=sys.stderr)
+              "(independent runs would shard by whole runs; no multi-GPU path is built)", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W
