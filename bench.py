@@ -259,7 +259,7 @@ def main():
                     help="end with a plain 256 MiB device copy, the reference kernel for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one MI355X only; runs on more than one GPU are not supported "
+        print("bench.py measures one MI355X only; runs on more than one GPU are not supported "
               "(independent runs would shard by whole runs; no multi-GPU path is built)", file=sys.stderr)
         sys.exit(2)
     import torch
