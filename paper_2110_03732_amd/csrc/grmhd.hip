@@ -166,6 +166,17 @@ bool needL(const Tableau &T, int j)
         if (T.At[m][j] != 0.0) return true;
     return false;
 }
+// must pass p store the L it evaluates (L of stage p-1)?  Only when a later
+// pass reads it: the final combination evaluates its own and is the last reader
+bool storeL_needed(const Tableau &T, int p)
+{
+    if (p < 1 || p >= T.s) return false;
+    const int j = p - 1;
+    if (T.wt[j] != 0.0) return true;
+    for (int q = p + 1; q < T.s; q++)
+        if (T.At[q][j] != 0.0) return true;
+    return false;
+}
 // are the faces of stage p those of time level n (no explicit term yet)?
 bool faces_are_n(const Tableau &T, int p)
 {
@@ -473,7 +484,7 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     A.s = T.s;
     A.fin = fin;
     A.withL = withL;
-    A.storeL = withL;
+    A.storeL = withL && storeL_needed(T, p);
     A.dt = dt;
     A.aii_dt = fin ? 0.0 : T.A[p][p] * dt;
     for (int j = 0; j < p && j < 4; j++) {
@@ -600,13 +611,13 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
         for (int d = 0; d < 3; d++) {
             for (int j = 0; j < 4; j++)
                 f.Ls.Lf[j][d] = (j < T.s) ? wfield(st, G, Ly.L + 11 * (size_t)j + 8 + d) : nullptr;
-            f.Ls.Lst[d] = withL ? wfield(st, G, Ly.L + 11 * (size_t)(p - 1) + 8 + d) : nullptr;
+            f.Ls.Lst[d] = A.storeL ? wfield(st, G, Ly.L + 11 * (size_t)(p - 1) + 8 + d) : nullptr;
         }
         f.fout = ptrs<3>(fout, G.fs);
         f.gd = flat_dims(f.R);
         double nf = 0.0;
         for (int d = 0; d < 3; d++) nf += (double)rtotal(region(G, 1 << d));
-        pl.fa_bytes = 8.0 * (nf * (1 + nLst + 1 + (int)withL) + (withL ? 3.0 * rtotal(f.R) : 0.0));
+        pl.fa_bytes = 8.0 * (nf * (1 + nLst + 1 + (int)A.storeL) + (withL ? 3.0 * rtotal(f.R) : 0.0));
     }
     // cells
     CellArgs &c = pl.ca;
@@ -636,7 +647,7 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     for (int v = 0; v < (fin ? 5 : Ly.nsp); v++) io.out[v] = out + v * G.fs;
     if (!fin)
         for (int i = 0; i < 3; i++) io.Rout[i] = wfield(st, G, Ly.R + 3 * (size_t)p + i);
-    if (withL)
+    if (A.storeL)
         for (int v = 0; v < nq; v++) io.Lout[v] = wfield(st, G, Ly.L + (size_t)Ly.nL * (p - 1) + v);
     io.met[0] = met;
     io.met[1] = met ? met + G.fs : nullptr;
@@ -655,7 +666,7 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     double cb = 8 + 3 + 2 * MET + nq * nLst + 3 * nRst + (fin ? 1 : 3) + ng;  // q, faces, metric, L, R, guess
     if (withL) cb += nq + Ly.nsp + 3;                                           // Lxy, stage p-1 block, faces
     cb += fin ? (8 + 5 + ng) : (Ly.nsp + 3 + (glm ? 3 : 0));                    // outputs
-    if (withL) cb += nq;                                                        // stored L
+    if (A.storeL) cb += nq;                                                     // stored L
     pl.ca_bytes = 8.0 * ncell * cb;
     return GR_OK;
 }
