@@ -177,6 +177,36 @@ bool storeL_needed(const Tableau &T, int p)
         if (T.At[q][j] != 0.0) return true;
     return false;
 }
+// Folded storage for the final combination.  The last implicit pass
+// pf = s - 1 reads the stored L_j / R_j it needs anyway; where these include
+// every term of the final combination but its own, it stores the final
+// combination's sum of them (L: slot of L_{pf-1}, R: slot of R_pf), and the
+// final pass reads that slot with weight 1 instead of one slot per stage.
+// Applied when it saves reads (two or more terms); the sums are the same up to
+// rounding order.
+bool foldL_applies(const Tableau &T)
+{
+    const int pf = T.s - 1;
+    if (!storeL_needed(T, pf)) return false;
+    int terms = 0;
+    for (int j = 0; j < pf; j++) {
+        if (T.wt[j] == 0.0) continue;
+        terms++;
+        if (j < pf - 1 && T.At[pf][j] == 0.0) return false;  // pf would need an extra read
+    }
+    return terms >= 2;
+}
+bool foldR_applies(const Tableau &T)
+{
+    const int pf = T.s - 1;
+    int terms = 0;
+    for (int j = 0; j <= pf; j++) {
+        if (T.w[j] == 0.0) continue;
+        terms++;
+        if (j < pf && T.A[pf][j] == 0.0) return false;
+    }
+    return terms >= 2;
+}
 // are the faces of stage p those of time level n (no explicit term yet)?
 bool faces_are_n(const Tableau &T, int p)
 {
@@ -490,6 +520,25 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     for (int j = 0; j < p && j < 4; j++) {
         A.cL[j] = fin ? T.wt[j] : T.At[p][j];
         A.cR[j] = fin ? T.w[j] : T.A[p][j];
+    }
+    const bool fL = foldL_applies(T), fR = foldR_applies(T);
+    if (p == T.s - 1) {
+        A.foldL = fL && A.storeL;
+        A.foldR = fR;
+        for (int j = 0; j < 4; j++) {
+            A.fL[j] = j < p ? T.wt[j] : 0.0;
+            A.fR[j] = j <= p ? T.w[j] : 0.0;
+        }
+    }
+    if (fin) {
+        if (fL) {
+            for (int j = 0; j < T.s - 1; j++) A.cL[j] = 0.0;
+            A.cL[T.s - 2] = 1.0;  // the folded sum in the slot of L_{s-2}
+        }
+        if (fR) {
+            for (int j = 0; j < T.s; j++) A.cR[j] = 0.0;
+            A.cR[T.s - 1] = 1.0;  // the folded sum in the slot of R_{s-1}
+        }
     }
     const bool glm = g->glm != 0;
     // face block of stage j: the state's own faces while no explicit term has

@@ -884,6 +884,12 @@ struct StageArgs {
     int p, s, fin, withL, storeL;
     double dt, aii_dt;
     double cL[4], cR[4];  // weights of L_j and R_j (j < p); final pass: wt, w
+    // folded storage (the last implicit pass): the stored L is sum_j fL_j L_j
+    // (j < p, the stored ones and the one evaluated here) and the stored R is
+    // sum_j fR_j R_j (j <= p), the final combination's part, which then reads
+    // one L and one R slot instead of one per stage
+    int foldL, foldR;
+    double fL[4], fR[4];
 };
 
 // CT update of the face fields (eq. ct), all three directions in one pass:
@@ -926,14 +932,17 @@ __device__ __forceinline__ void face_body(const FaceArgs &a, Blk blk)
             double t1 = G.act[m1] ? (ldb(EM.p[m2], o + ((unsigned)G.st[m1] << 3)) - ldb(EM.p[m2], o)) * G.idx[m1] : 0.0;
             double t2 = G.act[m2] ? (ldb(EM.p[m1], o + ((unsigned)G.st[m2] << 3)) - ldb(EM.p[m1], o)) * G.idx[m2] : 0.0;
             Lnew = -(t1 - t2);
-            if (A.storeL) stb(Ls.Lst[d], o, Lnew);
         }
+        double fold = 0.0;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             if (j >= A.p || A.cL[j] == 0.0) continue;
-            double l = (A.withL && j == A.p - 1) ? Lnew : ldb(Ls.Lf[j][d], o);
+            const bool fresh = A.withL && j == A.p - 1;
+            double l = fresh ? Lnew : ldb(Ls.Lf[j][d], o);
             acc += A.dt * A.cL[j] * l;
+            if (A.foldL && !fresh) fold += A.fL[j] * l;
         }
+        if (A.storeL) stb(Ls.Lst[d], o, A.foldL ? fold + A.fL[A.p - 1] * Lnew : Lnew);
         stb(fout.p[d], o, acc);
     }
 }
@@ -1106,13 +1115,12 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
             // s_tau = -psi^6 S^j d_j alpha = -psi^4 S_on . grad alpha
             Lc[4] += ps4 * sdt;
         }
-        if (A.storeL) {
-#pragma unroll
-            for (int v8 = 0; v8 < NQ; v8++) stb(io.Lout[v8], o, Lc[v8]);
-        }
     }
-    // accumulation q* = q^n + dt sum_j (cL_j L_j + cR_j R_j)
-    double qs[NQ];
+    // accumulation q* = q^n + dt sum_j (cL_j L_j + cR_j R_j), with the folded
+    // sums of the stored L and R where this pass keeps them
+    double qs[NQ], Lfold[NQ], Rfold[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < NQ; v++) Lfold[v] = 0.0;
 #pragma unroll
     for (int v = 0; v < 8; v++) qs[v] = ldb(io.q[v], o);
     if (GLM) {
@@ -1131,14 +1139,27 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
                 for (int v = 0; v < NQ; v++) qs[v] += w * Lc[v];
             } else {
 #pragma unroll
-                for (int v = 0; v < NQ; v++) qs[v] += w * ldb(io.Lc[j][v], o);
+                for (int v = 0; v < NQ; v++) {
+                    const double l = ldb(io.Lc[j][v], o);
+                    qs[v] += w * l;
+                    if (A.foldL) Lfold[v] += A.fL[j] * l;
+                }
             }
         }
         if (A.cR[j] != 0.0) {
             double w = A.dt * A.cR[j];
 #pragma unroll
-            for (int i = 0; i < 3; i++) qs[5 + i] += w * ldb(io.Rj[j][i], o);
+            for (int i = 0; i < 3; i++) {
+                const double r = ldb(io.Rj[j][i], o);
+                qs[5 + i] += w * r;
+                if (A.foldR) Rfold[i] += A.fR[j] * r;
+            }
         }
+    }
+    if (A.storeL) {
+        const double wf = A.foldL ? A.fL[A.p - 1] : 1.0;
+#pragma unroll
+        for (int v8 = 0; v8 < NQ; v8++) stb(io.Lout[v8], o, A.foldL ? Lfold[v8] + wf * Lc[v8] : Lc[v8]);
     }
     // orthonormal frame: B of this pass, D, tau, S, E*
     double B[3];
@@ -1202,7 +1223,8 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         for (int i = 0; i < 3; i++) {
             double Ec = ev.E[i] * ips2;
             stb(io.out[5 + i], o, Ec);
-            stb(io.Rout[i], o, (ps6 * Ec - qs[5 + i]) * iadt);
+            const double Rn = (ps6 * Ec - qs[5 + i]) * iadt;
+            stb(io.Rout[i], o, A.foldR ? Rfold[i] + A.fR[A.p] * Rn : Rn);
         }
         return;
     }
@@ -1256,7 +1278,8 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         for (int i = 0; i < 3; i++) {
             double Ec = E[i] * ips2;
             stb(io.out[5 + i], o, Ec);
-            stb(io.Rout[i], o, (ps6 * Ec - qs[5 + i]) * iadt);  // R = psi^6 (E - E*)/(a_ii dt)
+            const double Rn = (ps6 * Ec - qs[5 + i]) * iadt;  // R = psi^6 (E - E*)/(a_ii dt)
+            stb(io.Rout[i], o, A.foldR ? Rfold[i] + A.fR[A.p] * Rn : Rn);
         }
     } else {
 #pragma unroll
