@@ -74,6 +74,20 @@ def test_validation_rejects_bad_grids():
     assert grmhd.gr_workspace_bytes(g2) == 0
 
 
+def test_validation_size_limits():
+    """a field must stay below 2^32 bytes (32-bit offsets: at most 5e8 padded
+    points) and the padded z extent is a launch-grid dimension (<= 65535)"""
+    s = W.tov_star(16)
+    g = grmhd.grid_of(s)
+    for n, ok in [((780, 780, 780), True), ((800, 800, 800), False), ((4, 4, 65529), True), ((4, 4, 65530), False)]:
+        g.n[0], g.n[1], g.n[2] = n
+        pts = (n[0] + 2 * g.ng) * (n[1] + 2 * g.ng) * (n[2] + 2 * g.ng)
+        assert (pts <= 5e8 and n[2] + 2 * g.ng <= 65535) == ok
+        assert (grmhd.gr_validate(g) == 0) == ok, n
+    g.n[0] = g.n[1] = g.n[2] = 0
+    assert grmhd.gr_validate(g) == grmhd.GR_EINVAL  # empty grid
+
+
 @pytest.mark.parametrize("make", [lambda: W.shock_tube(400), lambda: W.blast_wave(512), lambda: W.tov_star(32),
                                   lambda: W.glm_monopole(24, ndim=3), lambda: W.glm_wave(64)])
 def test_layout(make):
