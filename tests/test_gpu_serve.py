@@ -53,3 +53,22 @@ def test_served_equals_alone():
                 assert np.abs(got[f] - want[f]).max() <= 1e-13 * max(np.abs(want[f]).max(), 1e-300), rec["rid"]
         assert run.fail_count() == rec["fails"]
         assert rec["latency"] > 0.0 and rec["done"] >= rec["admit"] >= rec["arrival"] - 1e-9
+
+
+def test_serve_edge_cases():
+    """an empty trace, a request of zero steps (finishes with its initial
+    state), a request larger than the whole budget (refused)"""
+    _torch()
+    from paper_2110_03732_amd import grmhd, serve
+    srv = serve.Server(1 << 30, chunk=2, keep=True)
+    recs, summary = srv.serve([], lambda r: None)
+    assert recs == [] and summary["requests"] == 0 and summary["p50_latency_s"] is None
+    s = W.blast_wave(24, eta=1e-2, imex=W.SSP2)
+    req = {"rid": 0, "arrival": 0.0, "steps": 0}
+    recs, summary = srv.serve([req], lambda r: s)
+    assert summary["requests"] == 1 and recs[0]["fails"] == 0
+    ref = grmhd.Run(s, device="cuda:0")
+    assert np.array_equal(recs[0]["prims"], ref.prims()) and np.array_equal(recs[0]["faces"], ref.faces())
+    tiny = serve.Server(1024, chunk=2)
+    with pytest.raises(ValueError):
+        tiny.serve([dict(req, steps=3)], lambda r: s)
