@@ -7,7 +7,8 @@ ulp in a few places, which can move a Newton stopping decision, so the
 comparison allows 1e-13 of each field's scale.  Two batches holding the same
 run compute it with the same kernels: that comparison is exact.  The batch
 mixes dimensions, reconstructions, sizes, resistivities and (with the star)
-the metric; one run is checked against the CPU oracle as well.
+the metric, and the dynamo term; one run is checked against the CPU oracle as
+well.
 """
 import os
 import sys
@@ -39,6 +40,11 @@ def _mix(imex):
     setups = [W.make_run_setup(p, imex=imex) for p in prm]
     setups.append(W.tov_star(20, imex=imex))
     setups.append(W.current_sheet(96, recon=W.MC, imex=imex))
+    # the mean-field dynamo instances: frozen matter, and a moving fluid
+    setups.append(W.steady_dynamo(64, imex=imex))
+    b = W.blast_wave(32, eta=1e-2, imex=imex)
+    b.xi = 0.05
+    setups.append(b)
     return setups
 
 
