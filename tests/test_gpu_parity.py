@@ -197,7 +197,7 @@ def test_one_step_parity(name):
 
 @pytest.mark.parametrize("name", ["shock_tube_400_minmod_ssp2", "blast_48_ppm_ssp3_eta1e-2", "star_24_cowling",
                                   "dynamo_k1_frozen_xi0.5", "blast_48_ppm_ssp3_eta1e-2_uct_ideal",
-                                  "star_24_cowling_uct_ideal"])
+                                  "star_24_cowling_uct_ideal", "loop_periodic_40x20"])
 def test_hundred_steps_parity(name):
     _torch()
     say("case %s: 100 steps" % name)
@@ -352,3 +352,37 @@ def test_full_size_parity(name):
     assert run.divB()[2] <= 1e-12
     assert run.fail_count() == ref.nfail
     say("  rel L1 %s" % ["%.1e" % e for e in errs])
+
+
+@pytest.mark.parametrize("name", ["tov_star_128_ppm_ssp3", "blast_512_ppm_ssp3_stiff", "loop_512x256_periodic"])
+def test_full_size_hundred_steps_invariants(name):
+    """100 steps of the benchmark workloads at full size (the 128^3 star: the
+    benchmark's own step): properties that hold at any size, against no
+    oracle: div B at round-off (CT), no recovery failures, finite states; on
+    the periodic loop the totals of q_D, q_tau and every face field kept"""
+    _torch()
+    say("full-size 100 steps %s" % name)
+    if name.startswith("tov"):
+        s = W.tov_star(128)
+    elif name.startswith("blast"):
+        s = W.blast_wave(512, eta=1e-6)
+    else:
+        s = W.loop_advection(512, 256)
+    run = gpu_run(s)
+    dt = run.dt()
+    sl = s.interior
+    tot0 = None
+    if name.startswith("loop"):
+        q, f = run.cons(), run.faces()
+        tot0 = [q[0][sl].sum(), q[4][sl].sum()] + [f[d][sl].sum() for d in range(3)]
+    for _ in range(100):
+        run.step(dt)
+    assert run.divB()[2] <= 1e-12
+    assert run.fail_count() == 0
+    p = run.prims()
+    assert np.all(np.isfinite(p[:, sl[0], sl[1], sl[2]]))
+    if tot0 is not None:
+        q, f = run.cons(), run.faces()
+        tot1 = [q[0][sl].sum(), q[4][sl].sum()] + [f[d][sl].sum() for d in range(3)]
+        for a, b in zip(tot0, tot1):
+            assert abs(a - b) <= 1e-13 * s.ncells * max(abs(a), 1e-3)
