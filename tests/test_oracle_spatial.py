@@ -132,7 +132,7 @@ def test_ct_keeps_div_b_and_periodic_totals():
     dt = st.dt()
     d0 = st.divB()
     tot0 = [interior(s, a).sum() for a in st.q[:5] + st.face]
-    for _ in range(40):
+    for _ in range(100):
         st.step(dt)
     d1 = st.divB()
     assert d0[2] <= 1e-12 and d1[2] <= 1e-12
