@@ -3,6 +3,8 @@ logic (validation, layout) behaves; no device calls (runs without a GPU)."""
 import ctypes
 import os
 import re
+import subprocess
+import tempfile
 
 import pytest
 
@@ -151,3 +153,16 @@ def test_batch_create_rejects_bad_arguments():
     assert L.gr_batch_create(ctypes.byref(h), ga, sa3, da, 1, None, None) == grmhd.GR_ENOMEM
     assert h.value is None
     assert L.gr_batch_destroy(None) == grmhd.GR_OK
+
+
+def test_header_is_plain_c():
+    """include/grmhd.h compiles as C99 with warnings as errors (the boundary
+    needs no C++ or PyTorch type)"""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "t.c")
+        with open(src, "w") as f:
+            f.write('#include "grmhd.h"\nint main(void) { gr_grid g; (void)g; return gr_abi_version() > 0 ? 0 : 1; }\n')
+        subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
+                               "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                               "-I", os.path.join(rocm, "include"), src])
