@@ -48,7 +48,7 @@ def _rel(a, b, floor):
     return np.abs(a - b).sum() / max(np.abs(b).sum(), b.size * floor)
 
 
-@pytest.mark.parametrize("i", range(24))
+@pytest.mark.parametrize("i", range(48))
 def test_sweep(i):
     import torch
     if not torch.cuda.is_available():
