@@ -9,9 +9,11 @@
 //   pass p = s : L of stage s-1 -> final combination -> recovery with E, B
 //                known (Sec 2.6)
 // The explicit operator (Sec 2.1 fluxes and sources, Sec 2.5 speeds, HLL,
-// Sec 3.2 upwind constrained transport): one ghost-fill launch, one LDS sweep
-// per direction (reconstruction + HLL -> face fluxes), a-face electric field
-// states, edge EMFs, the CT face update and the cell pass.
+// Sec 3.2 upwind constrained transport): one ghost-fill launch, the x/y LDS
+// sweeps (reconstruction + HLL, flux divergence written), one EMF launch per
+// edge direction, the CT face update, and the cell pass that runs the z sweep
+// and the sources before the accumulation.  GLM cleaning (Sec 3.1) replaces
+// the EMF and face-update launches by three more swept components.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -5,12 +5,14 @@
 //   k_xy          x and y phases of the explicit operator on an LDS-staged
 //                 tile: reconstruction of the ten face variables, HLL flux
 //                 on every face, flux divergence
-//   k_ct          upwind constrained-transport EMF on the edges
+//   k_ct          upwind constrained-transport EMF on the edges (Sec 3.2;
+//                 the ideal-MHD form of App. A as the IDEAL instances)
 //   k_face_update CT update of the face fields + stage accumulation
 //   k_cell_update z phase of the explicit operator (3-D), Cowling sources,
 //                 stage accumulation, fused implicit E + velocity Newton
-//                 solve or final recovery
-// Paper: Cheong et al., arXiv:2110.03732, Sec 2.1-2.6 and Sec 3.2.
+//                 solve (with the dynamo terms as the XI instances) or final
+//                 recovery; GLM instances carry the cell-centred B, Psi, Phi
+// Paper: Cheong et al., arXiv:2110.03732, Sec 2.1-2.6, Sec 3.1-3.2, App. A.
 #pragma once
 #include "common.h"
 #include "physics.h"
