@@ -255,6 +255,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="star workload only (no 2-D point, no roofline replay)")
     ap.add_argument("--no-many", action="store_true", help="skip the batched and served comparisons")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served comparison")
     ap.add_argument("--batch-runs", type=int, default=256, help="runs in the batched-vs-plain comparison")
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=160)
@@ -310,8 +311,9 @@ def main():
     if not args.no_extra and not args.no_many:
         print("bench: batched vs plain", file=sys.stderr, flush=True)
         extra["batched"] = batched_vs_plain(torch, W, grmhd, args.batch_runs, args.batch_steps)
-        print("bench: served", file=sys.stderr, flush=True)
-        extra["served"] = served(torch, W, grmhd, args.serve_requests, args.serve_rate, (32.0, 2.0))
+        if not args.no_serve:
+            print("bench: served", file=sys.stderr, flush=True)
+            extra["served"] = served(torch, W, grmhd, args.serve_requests, args.serve_rate, (32.0, 2.0))
     if args.copy_ref:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
         b = torch.empty_like(a)
