@@ -475,12 +475,56 @@ void with_flag(int flag, F &&f)
 
 const int kCtOrder[3] = {2, 0, 1};
 
+// EMF kernel form of edge direction K: the ideal-MHD form when asked for,
+// otherwise one-cell-thick tiles when z (and y) are inactive
+int ct_form(const Geo &G, int uct, int K)
+{
+    if (uct) return CT_IDEAL;
+    if (!G.act[1]) return CT_LINE;
+    if (!G.act[2] && K != 2) return CT_PLANE;
+    return CT_BOX;
+}
+void ct_tile(int K, int F, int T[3])
+{
+    auto set = [&](auto KK, auto FF) {
+        for (int d = 0; d < 3; d++) T[d] = CtTileF<decltype(KK)::value, decltype(FF)::value>::T[d];
+    };
+    auto byF = [&](auto KK) {
+        if (F == CT_PLANE) set(KK, IC<CT_PLANE>{});
+        else if (F == CT_LINE) set(KK, IC<CT_LINE>{});
+        else set(KK, IC<CT_BOX>{});
+    };
+    if (K == 0) byF(IC<0>{});
+    else if (K == 1) byF(IC<1>{});
+    else byF(IC<2>{});
+}
+// calls f(IC<K>, IC<F>) for the compiled (edge direction, form) pairs: the
+// planar form has no z-edge instance (z-edges of a plane use the box form),
+// the line form no x-edge one (a line has no x-edges)
+template <class Fn>
+void with_ct(int K, int F, Fn &&f)
+{
+    auto byF = [&](auto KK) {
+        constexpr int k = decltype(KK)::value;
+        if (F == CT_IDEAL) f(KK, IC<CT_IDEAL>{});
+        else if (F == CT_PLANE) {
+            if constexpr (k != 2) f(KK, IC<CT_PLANE>{});
+        } else if (F == CT_LINE) {
+            if constexpr (k != 0) f(KK, IC<CT_LINE>{});
+        } else f(KK, IC<CT_BOX>{});
+    };
+    if (K == 0) byF(IC<0>{});
+    else if (K == 1) byF(IC<1>{});
+    else byF(IC<2>{});
+}
+
 // Everything one pass of one run launches, in launch order: ghost fill,
 // x/y phases, the three EMF components, the face update, the cell pass.
 struct PassPlan {
     bool ghost = false, xy = false, face = false;
     bool swz = false;  // cell pass with the z phase
     bool ct[3] = {false, false, false};
+    int ctf[3] = {CT_BOX, CT_BOX, CT_BOX};  // EMF kernel form per launch
     GhostArgs gh;
     XyArgs xya;
     CtArgs cta[3];
@@ -635,7 +679,9 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
             c.sf = cptrs<3>(sf_prev, G.fs);
             c.met = cptrs<2>(met, G.fs);
             c.EM = EM + (size_t)K * G.fs;
-            const int *Tt = K == 2 ? CtTile<2>::T : (K == 0 ? CtTile<0>::T : CtTile<1>::T);
+            pl.ctf[i] = ct_form(G, g->uct, K);
+            int Tt[3];
+            ct_tile(K, pl.ctf[i], Tt);
             c.gd.x = (c.R.cnt[0] + Tt[0] - 1) / Tt[0];
             c.gd.y = (c.R.cnt[1] + Tt[1] - 1) / Tt[1];
             c.gd.z = (c.R.cnt[2] + Tt[2] - 1) / Tt[2];
@@ -739,15 +785,13 @@ void launch_xy(const Variant &V, const XyArgs &a, hipStream_t s)
         });
     });
 }
-void launch_ct(const Variant &V, int K, const CtArgs &a, hipStream_t s)
+void launch_ct(const Variant &V, int K, int F, const CtArgs &a, hipStream_t s)
 {
     with_rm(V.rec, V.met, [&](auto R, auto M) {
-        with_flag(V.uct, [&](auto U) {
-            constexpr int r = decltype(R)::value, m = decltype(M)::value;
-            constexpr bool u = decltype(U)::value != 0;
-            if (K == 2) hipLaunchKernelGGL((k_ct<r, m, 2, u>), d3(a.gd), dim3(kBlock), 0, s, a);
-            else if (K == 0) hipLaunchKernelGGL((k_ct<r, m, 0, u>), d3(a.gd), dim3(kBlock), 0, s, a);
-            else hipLaunchKernelGGL((k_ct<r, m, 1, u>), d3(a.gd), dim3(kBlock), 0, s, a);
+        with_ct(K, F, [&](auto KK, auto FF) {
+            hipLaunchKernelGGL((k_ct<decltype(R)::value, decltype(M)::value, decltype(KK)::value,
+                                     decltype(FF)::value>),
+                               d3(a.gd), dim3(kBlock), 0, s, a);
         });
     });
 }
@@ -796,7 +840,7 @@ gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
     for (int i = 0; i < 3; i++) {
         if (!pl.ct[i]) continue;
         TScope ts(KC_CT, s, pl.ct_bytes[i]);
-        launch_ct(V, kCtOrder[i], pl.cta[i], s);
+        launch_ct(V, kCtOrder[i], pl.ctf[i], pl.cta[i], s);
         LAUNCHCHK();
     }
     if (pl.face) {
@@ -830,7 +874,7 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
 // list is captured once into a HIP graph and replayed per step.
 struct BLaunch {
     int cls = 0;
-    int K = 0;
+    int K = 0, F = 0;  // EMF launches: edge direction and kernel form
     Variant V{};
     bool swz = false;
     size_t args_off = 0, start_off = 0;  // offsets into the batch's device block
@@ -942,17 +986,17 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
                             add_group(stg, out, L, a, by);
                         }
         }
-        // EMFs, grouped by (component, recon, metric)
+        // EMFs, grouped by (component, recon, metric, kernel form)
         if (cls_mask & (1u << KC_CT)) {
             for (int i = 0; i < 3; i++)
                 for (int rec = 0; rec < 3; rec++)
                     for (int met = 0; met < 2; met++)
-                        for (int uct = 0; uct < 2; uct++) {
+                        for (int f = CT_BOX; f <= CT_LINE; f++) {
                             std::vector<const CtArgs *> a;
                             std::vector<double> by;
                             for (int r = 0; r < nr; r++) {
                                 const Variant &V = b->var[r];
-                                if (use[r] && pl[r].ct[i] && V.rec == rec && V.met == met && V.uct == uct) {
+                                if (use[r] && pl[r].ct[i] && V.rec == rec && V.met == met && pl[r].ctf[i] == f) {
                                     a.push_back(&pl[r].cta[i]);
                                     by.push_back(pl[r].ct_bytes[i]);
                                 }
@@ -960,7 +1004,8 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
                             BLaunch L;
                             L.cls = KC_CT;
                             L.K = kCtOrder[i];
-                            L.V = Variant{rec, met, 0, 0, 0, 0, uct};
+                            L.F = f;
+                            L.V = Variant{rec, met, 0, 0, 0, 0, f == CT_IDEAL};
                             add_group(stg, out, L, a, by);
                         }
         }
@@ -1049,13 +1094,10 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
         break;
     case KC_CT:
         with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
-            with_flag(L.V.uct, [&](auto U) {
-                constexpr int r = decltype(R)::value, m = decltype(M)::value;
-                constexpr bool u = decltype(U)::value != 0;
-                const CtArgs *a = (const CtArgs *)L.args;
-                if (L.K == 2) hipLaunchKernelGGL((kb_ct<r, m, 2, u>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
-                else if (L.K == 0) hipLaunchKernelGGL((kb_ct<r, m, 0, u>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
-                else hipLaunchKernelGGL((kb_ct<r, m, 1, u>), grid, dim3(kBlock), 0, s, a, L.start, L.n);
+            with_ct(L.K, L.F, [&](auto KK, auto FF) {
+                hipLaunchKernelGGL((kb_ct<decltype(R)::value, decltype(M)::value, decltype(KK)::value,
+                                          decltype(FF)::value>),
+                                   grid, dim3(kBlock), 0, s, (const CtArgs *)L.args, L.start, L.n);
             });
         });
         break;

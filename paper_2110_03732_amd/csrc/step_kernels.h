@@ -6,7 +6,8 @@
 //                 tile: reconstruction of the ten face variables, HLL flux
 //                 on every face, flux divergence
 //   k_ct          upwind constrained-transport EMF on the edges (Sec 3.2;
-//                 the ideal-MHD form of App. A as the IDEAL instances)
+//                 the ideal-MHD form of App. A as the CT_IDEAL instances;
+//                 one-cell-thick tiles on planes and lines)
 //   k_face_update CT update of the face fields + stage accumulation
 //   k_cell_update z phase of the explicit operator (3-D), Cowling sources,
 //                 stage accumulation, fused implicit E + velocity Newton
@@ -386,7 +387,8 @@ __device__ __forceinline__ void face_metric(const Geo &G, const CPtr<2> &met, un
 // to LDS; then each edge reconstructs them along b (the LL, LR, RL, RR
 // states), q_B^a along b and q_B^b along a, and combines them with the
 // metric-only speeds (c+ = c-).  ct_body stages every input in LDS;
-// ct_body_direct (x-edges) reads the cell values from memory.
+// ct_body_direct (x-edges of 3-D grids, and the edges of planes and lines
+// along an inactive direction) reads the cell values from memory.
 template <int K>
 struct CtTile;
 template <>
@@ -401,6 +403,25 @@ template <>
 struct CtTile<0> {  // x-edges: a = y, b = z
     static constexpr int T[3] = {16, 2, 8};
 };
+
+// Edge-EMF kernel forms.  CT_BOX: the tiles above (x-edges direct, the others
+// staged); CT_IDEAL: the ideal-MHD form of App. A on the same tiles; CT_PLANE
+// (z inactive: the x- and y-edges) and CT_LINE (y and z inactive: the y- and
+// z-edges): the direct body on one-cell-thick tiles, the inactive directions
+// known at compile time so that no halo is staged along them.
+enum { CT_BOX = 0, CT_IDEAL = 1, CT_PLANE = 2, CT_LINE = 3 };
+template <int K, int F>
+struct CtTileF {
+    static constexpr int T[3] = {F == CT_PLANE ? 64 : (F == CT_LINE ? 256 : CtTile<K>::T[0]),
+                                 F == CT_PLANE ? 4 : (F == CT_LINE ? 1 : CtTile<K>::T[1]),
+                                 F == CT_PLANE || F == CT_LINE ? 1 : CtTile<K>::T[2]};
+};
+// direction d inactive in every grid the form is launched on
+template <int F>
+__host__ __device__ constexpr bool ct_flat(int d)
+{
+    return (F == CT_PLANE && d == 2) || (F == CT_LINE && d >= 1);
+}
 
 struct CtArgs {
     Geo G;
@@ -552,7 +573,7 @@ __device__ __forceinline__ void ct_ideal_body(const CtArgs &args, Blk blk)
 // halo), the left/right states of psi^4 E_K reconstructed along a and q_B^a
 // in LDS; step 2 reconstructs them along b, q_B^b along a from memory, and
 // combines them with the metric-only speeds.
-template <int REC, int MET, int K>
+template <int REC, int MET, int K, int F>
 __device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
 {
     const Geo &G = args.G;
@@ -561,8 +582,8 @@ __device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
     const CPtr<3> &sf = args.sf;
     const CPtr<2> &met = args.met;
     constexpr int A = (K + 1) % 3, B = (K + 2) % 3;
-    constexpr int T0 = CtTile<K>::T[0], T1 = CtTile<K>::T[1], T2 = CtTile<K>::T[2];
-    constexpr int HB = 3;
+    constexpr int T0 = CtTileF<K, F>::T[0], T1 = CtTileF<K, F>::T[1], T2 = CtTileF<K, F>::T[2];
+    constexpr int HB = ct_flat<F>(B) ? 0 : 3;
     constexpr int E0 = T0 + (B == 0 ? 2 * HB : 0), E1 = T1 + (B == 1 ? 2 * HB : 0), E2 = T2 + (B == 2 ? 2 * HB : 0);
     constexpr int NL = E0 * E1 * E2;
     constexpr int SB = (B == 0) ? 1 : (B == 1 ? E0 : E0 * E1);  // LDS stride along b
@@ -571,7 +592,7 @@ __device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
 
     const int tid = threadIdx.x;
     const int org[3] = {R.lo[0] + (int)blk.x * T0, R.lo[1] + (int)blk.y * T1, R.lo[2] + (int)blk.z * T2};
-    const bool actA = G.act[A], actB = G.act[B];
+    const bool actA = !ct_flat<F>(A) && G.act[A], actB = !ct_flat<F>(B) && G.act[B];
 
     // ---- step 1: a-face states of psi^4 E_k and q_B^a, clamped into range
     for (int l = tid; l < NL; l += kBlock) {
@@ -864,21 +885,24 @@ __device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
     stb(args.EM, o, ae * 0.25 * (ELL + ELR + ERL + ERR) + 0.5 * ca * (qbR - qbL) - 0.5 * cb * (qaR - qaL));
 }
 
-template <int REC, int MET, int K, bool IDEAL>
+template <int REC, int MET, int K, int F>
+__device__ __forceinline__ void ct_dispatch(const CtArgs &a, Blk blk)
+{
+    if constexpr (F == CT_IDEAL) ct_ideal_body<REC, MET, K>(a, blk);
+    else if constexpr (F != CT_BOX || K == 0) ct_body_direct<REC, MET, K, F>(a, blk);
+    else ct_body<REC, MET, K>(a, blk);
+}
+template <int REC, int MET, int K, int F>
 __global__ void __launch_bounds__(kBlock) k_ct(CtArgs a)
 {
-    if constexpr (IDEAL) ct_ideal_body<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
-    else if constexpr (K == 0) ct_body_direct<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
-    else ct_body<REC, MET, K>(a, blk_of(hw_linear<true>(), a.gd));
+    ct_dispatch<REC, MET, K, F>(a, blk_of(hw_linear<true>(), a.gd));
 }
-template <int REC, int MET, int K, bool IDEAL>
+template <int REC, int MET, int K, int F>
 __global__ void __launch_bounds__(kBlock) kb_ct(const CtArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
 {
     unsigned lb;
     const CtArgs &a = aa[batch_locate<true>(start, n, lb)];
-    if constexpr (IDEAL) ct_ideal_body<REC, MET, K>(a, blk_of(lb, a.gd));
-    else if constexpr (K == 0) ct_body_direct<REC, MET, K>(a, blk_of(lb, a.gd));
-    else ct_body<REC, MET, K>(a, blk_of(lb, a.gd));
+    ct_dispatch<REC, MET, K, F>(a, blk_of(lb, a.gd));
 }
 
 // ---------------------------------------------------------------------------
