@@ -39,6 +39,9 @@ def _mix(imex):
     prm = W.batch_mix_params(6, seed=3, n1=(100, 700), n2=(40, 90))
     setups = [W.make_run_setup(p, imex=imex) for p in prm]
     setups.append(W.tov_star(20, imex=imex))
+    # the metric on a plane and on a line (planar and line EMF tiles)
+    setups.append(W.tov_star(24, ndim=2, imex=imex))
+    setups.append(W.tov_star(90, ndim=1, imex=imex))
     setups.append(W.current_sheet(96, recon=W.MC, imex=imex))
     # the mean-field dynamo instances: frozen matter, and a moving fluid
     setups.append(W.steady_dynamo(64, imex=imex))

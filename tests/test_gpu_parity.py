@@ -86,6 +86,12 @@ CASES = {
     "charged_vortex_32_fixed": lambda: W.charged_vortex(32),
     "star_24_cowling": lambda: W.tov_star(24),
     "star_13x11x9_ragged": lambda: _ragged_star(),
+    # the star on its equatorial plane and on the x axis (metric with
+    # inactive directions: planar and line EMF tiles, one-row x/y tiles)
+    "star_2d_40_cowling": lambda: _star_slice(40, 2),
+    "star_2d_33_mc_ssp2_cowling": lambda: _star_slice(33, 2, recon=W.MC, imex=W.SSP2),
+    "star_1d_150_cowling": lambda: _star_slice(150, 1),
+    "star_1d_97_minmod_ssp2_cowling": lambda: _star_slice(97, 1, recon=W.MINMOD, imex=W.SSP2),
     "dynamo_k1_frozen_xi0.5": lambda: W.steady_dynamo(64, k=1),
     "blast_48_ppm_ssp3_xi0.05": lambda: _with(W.blast_wave(48, eta=1e-2), xi=0.05),
     # degenerate and minimal shapes: one-cell-thick active directions, periodic
@@ -104,7 +110,21 @@ CASES = {
     "loop_periodic_40x20_uct_ideal": lambda: _with(W.loop_advection(40, 20), uct=1),
     "star_24_cowling_uct_ideal": lambda: _with(W.tov_star(24), uct=1),
     "star_13x11x9_ragged_uct_ideal": lambda: _with(_ragged_star(), uct=1),
+    "star_2d_40_cowling_uct_ideal": lambda: _with(_star_slice(40, 2), uct=1),
+    "star_1d_150_cowling_uct_ideal": lambda: _with(_star_slice(150, 1), uct=1),
 }
+
+
+def _star_slice(n, ndim, **kw):
+    """the Cowling star on z = 0 (ndim 2) or on the x axis (ndim 1), with a
+    small velocity inside the star"""
+    s = W.tov_star(n, ndim=ndim, **kw)
+    X, Y, _ = s.mesh()
+    w = s.prim[0] / s.prim[0].max()
+    s.prim[1] = 0.01 * np.sin(X / 3) * w
+    if ndim >= 2:
+        s.prim[2] = -0.008 * np.sin(Y / 2.5) * w
+    return s
 
 
 def _smooth_box(ndim, n, bc, recon=W.MC, imex=W.SSP2):
@@ -197,7 +217,8 @@ def test_one_step_parity(name):
 
 @pytest.mark.parametrize("name", ["shock_tube_400_minmod_ssp2", "blast_48_ppm_ssp3_eta1e-2", "star_24_cowling",
                                   "dynamo_k1_frozen_xi0.5", "blast_48_ppm_ssp3_eta1e-2_uct_ideal",
-                                  "star_24_cowling_uct_ideal", "loop_periodic_40x20"])
+                                  "star_24_cowling_uct_ideal", "loop_periodic_40x20", "star_2d_40_cowling",
+                                  "star_1d_150_cowling"])
 def test_hundred_steps_parity(name):
     _torch()
     say("case %s: 100 steps" % name)

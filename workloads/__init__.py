@@ -308,18 +308,22 @@ _TOV_CACHE = {}
 
 
 def tov_star(n=128, ext=12.0, b_max=1e-4, rho_atm=1e-10, steps=200, recon=PPM, imex=SSP3, sigma0=1e6,
-             eta_in=1e-6, eta_out=1.0, atm_factor=1e4):
+             eta_in=1e-6, eta_out=1.0, atm_factor=1e4, ndim=3):
     """3-D magnetised polytropic star (K = 100, Gamma = 2, rho_c = 1.28e-3) in
     a static conformally flat metric, poloidal field from
     A_phi = A_b varpi^2 max(p - 0.04 p_c, 0)^2 scaled so max|B| = b_max,
-    atmosphere rho_atm, eta from sigma(D) clamped to [eta_in, eta_out]."""
+    atmosphere rho_atm, eta from sigma(D) clamped to [eta_in, eta_out].
+    ndim 2 / 1: the same star on its equatorial plane z = 0 / on the x axis
+    (the inactive coordinates are 0), n cells per active direction."""
     key = ("tov",)
     if key not in _TOV_CACHE:
         _TOV_CACHE[key] = tov_profile()
     T = _TOV_CACHE[key]
     K, G = T["K"], T["Gamma"]
-    s = _blank(Setup("tov_star", 3, (n, n, n), 3 if recon == PPM else 2, (-ext,) * 3, (ext,) * 3,
-                     _bc(3, OUTFLOW), 2.0, recon, imex, eta_mode=1, eta=eta_in, sigma0=sigma0,
+    shape = tuple(n if d < ndim else 1 for d in range(3))
+    s = _blank(Setup("tov_star" if ndim == 3 else "tov_star_%dd" % ndim, ndim, shape, 3 if recon == PPM else 2,
+                     (-ext,) * 3, (ext,) * 3, _bc(ndim, OUTFLOW), 2.0, recon, imex, eta_mode=1, eta=eta_in,
+                     sigma0=sigma0,
                      eta_min=eta_in, eta_max=eta_out, rho_atm=rho_atm, p_atm=K * rho_atm ** G, metric=1,
                      steps=steps, atm_factor=atm_factor))
     X, Y, Z = s.mesh()
