@@ -160,17 +160,20 @@ __device__ __forceinline__ void hll_face(const Phys &P, const double *sL, const 
 
 // cell-centred B^t (contravariant) of the cell at coordinates c: the mean of
 // the two faces / psi^6 (the +1 face index kept inside the array), or with
-// GLM the cell value / psi^6
+// GLM the cell value / psi^6.  Branch-free: along an inactive t both loads
+// read the cell's own value and 0.5 (b + b) = b exactly, so the loads of a
+// staging round never wait behind a branch.
 template <int MET, bool GLM = false>
 __device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const CPtr<2> &met, const int c[3], int t)
 {
     unsigned o = (unsigned)lin(G, c) << 3;
     double b;
-    if (G.act[t] && !GLM) {
-        int cc[3] = {c[0], c[1], c[2]};
-        if (cc[t] > G.N[t] - 2) cc[t] = G.N[t] - 2;
-        unsigned o0 = (unsigned)lin(G, cc) << 3;
-        b = 0.5 * (ldb(sf.p[t], o0) + ldb(sf.p[t], o0 + ((unsigned)G.st[t] << 3)));
+    if constexpr (!GLM) {
+        const bool act = G.act[t];
+        const unsigned top = c[t] > G.N[t] - 2 ? (unsigned)G.st[t] << 3 : 0u;  // +1 face kept inside
+        const unsigned o0 = act ? o - top : o;
+        const unsigned o1 = act ? o0 + ((unsigned)G.st[t] << 3) : o;
+        b = 0.5 * (ldb(sf.p[t], o0) + ldb(sf.p[t], o1));
     } else {
         b = ldb(sf.p[t], o);
     }
@@ -225,13 +228,16 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
     double(*raw)[NRAW] = reinterpret_cast<double(*)[NRAW]>(lds);
     const int tid = threadIdx.x;
 
-    // every load of the staging rounds is issued before the first LDS store
+    // every load of the staging rounds is issued, unconditionally, before the
+    // first LDS store (lanes past the end of the last round load its last
+    // point again and store nothing)
     constexpr int NR = (NRAW + NT - 1) / NT;
     double st[NR][NV];
 #pragma unroll
     for (int k = 0; k < NR; k++) {
-        const int l = tid + k * NT;
-        if (l < NRAW) {
+        int l = tid + k * NT;
+        if (k == NR - 1 && NRAW % NT != 0) l = l < NRAW ? l : NRAW - 1;
+        {
             int c[3] = {org[0] + l % E0, org[1] + (l / E0) % E1, org[2] + l / (E0 * E1)};
             c[D] -= H;
 #pragma unroll
@@ -704,41 +710,40 @@ struct CtBox {
 };
 
 // stage one cell-sized field over a box (coordinates clamped into the padded
-// array; clamped points only feed results that are never stored); all loads
-// of a thread are issued before its LDS stores
+// array; clamped points only feed results that are never stored), in two
+// halves: ct_load issues a lane's loads unconditionally (lanes past the box
+// end load its last point again), ct_store writes them to LDS.  A kernel
+// issues the loads of all its boxes before the first store, so a wave keeps
+// every load in flight at once.
 template <class BX>
-__device__ __forceinline__ void ct_stage(const Geo &G, const double *__restrict__ f, const int org[3], double *dst)
+struct CtRegs {
+    static constexpr int NR = (BX::N + kBlock - 1) / kBlock;
+    double v[NR];
+};
+template <class BX>
+__device__ __forceinline__ void ct_load(const Geo &G, const double *__restrict__ f, const int org[3], CtRegs<BX> &R)
 {
-    constexpr int NR = (BX::N + kBlock - 1) / kBlock;
+    constexpr int NR = CtRegs<BX>::NR;
     constexpr unsigned X0 = BX::X[0], X1 = BX::X[1];
     const int b[3] = {org[0] + BX::O[0], org[1] + BX::O[1], org[2] + BX::O[2]};
-    // most boxes lie inside the padded array: no clamping, one base offset
-    bool inner = true;
-#pragma unroll
-    for (int d = 0; d < 3; d++) inner = inner && b[d] >= 0 && b[d] + BX::X[d] <= G.N[d];
-    const unsigned base = inner ? (unsigned)lin(G, b) : 0u;
-    double v[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        const unsigned l = threadIdx.x + (unsigned)(r * kBlock);
-        if (l < (unsigned)BX::N) {
-            const unsigned e0 = l % X0, q = l / X0, e1 = q % X1, e2 = q / X1;
-            unsigned off;
-            if (inner) {
-                off = base + e0 + e1 * (unsigned)G.st[1] + e2 * (unsigned)G.st[2];
-            } else {
-                int c[3] = {b[0] + (int)e0, b[1] + (int)e1, b[2] + (int)e2};
+        unsigned l = threadIdx.x + (unsigned)(r * kBlock);
+        if (r == NR - 1 && BX::N % kBlock != 0) l = l < (unsigned)BX::N ? l : (unsigned)BX::N - 1;
+        const unsigned e0 = l % X0, q = l / X0, e1 = q % X1, e2 = q / X1;
+        int c[3] = {b[0] + (int)e0, b[1] + (int)e1, b[2] + (int)e2};
 #pragma unroll
-                for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
-                off = (unsigned)lin(G, c);
-            }
-            v[r] = ldb(f, off << 3);
-        }
+        for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
+        R.v[r] = ldb(f, (unsigned)lin(G, c) << 3);
     }
+}
+template <class BX>
+__device__ __forceinline__ void ct_store(const CtRegs<BX> &R, double *dst)
+{
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
+    for (int r = 0; r < CtRegs<BX>::NR; r++) {
         const int l = (int)threadIdx.x + r * kBlock;
-        if (l < BX::N) dst[l] = v[r];
+        if (l < BX::N) dst[l] = R.v[r];
     }
 }
 
@@ -768,12 +773,26 @@ __device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
     const int org[3] = {R.lo[0] + (int)blk.x * CtTile<K>::T[0], R.lo[1] + (int)blk.y * CtTile<K>::T[1],
                         R.lo[2] + (int)blk.z * CtTile<K>::T[2]};
     const bool actA = G.act[A], actB = G.act[B];
-    ct_stage<BE>(G, args.Ek, org, sE);
-    ct_stage<BQa>(G, args.sf.p[A], org, sQa);
-    ct_stage<BQb>(G, args.sf.p[B], org, sQb);
-    if (MET) {
-        ct_stage<BP>(G, args.met.p[1], org, sP);
-        ct_stage<BA>(G, args.met.p[0], org, sAl);
+    {
+        CtRegs<BE> rE;
+        CtRegs<BQa> rQa;
+        CtRegs<BQb> rQb;
+        CtRegs<BP> rP;
+        CtRegs<BA> rA;
+        ct_load<BE>(G, args.Ek, org, rE);
+        ct_load<BQa>(G, args.sf.p[A], org, rQa);
+        ct_load<BQb>(G, args.sf.p[B], org, rQb);
+        if (MET) {
+            ct_load<BP>(G, args.met.p[1], org, rP);
+            ct_load<BA>(G, args.met.p[0], org, rA);
+        }
+        ct_store<BE>(rE, sE);
+        ct_store<BQa>(rQa, sQa);
+        ct_store<BQb>(rQb, sQb);
+        if (MET) {
+            ct_store<BP>(rP, sP);
+            ct_store<BA>(rA, sAl);
+        }
     }
     __syncthreads();
 
