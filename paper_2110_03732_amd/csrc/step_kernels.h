@@ -1023,11 +1023,11 @@ struct CellIO {
     unsigned long long *nfail;
 };
 
-template <int MET, bool GLM = false>
+template <int MET, bool GLM = false, bool ALLACT = false>
 __device__ __forceinline__ double bcc_dev(const Geo &G, const double *const *face, double ip6, unsigned o, int t)
 {
-    double v = (G.act[t] && !GLM) ? 0.5 * (ldb(face[t], o) + ldb(face[t], o + ((unsigned)G.st[t] << 3)))
-                                  : ldb(face[t], o);
+    double v = ((ALLACT || G.act[t]) && !GLM) ? 0.5 * (ldb(face[t], o) + ldb(face[t], o + ((unsigned)G.st[t] << 3)))
+                                              : ldb(face[t], o);
     return MET ? v * ip6 : v;
 }
 
@@ -1051,6 +1051,10 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     const StageArgs &A = args.A;
     const CellIO &io = args.io;
     constexpr int NQ = NVar<GLM>::NF;
+    // the z-phase instances serve 3-D grids in passes with L: every direction
+    // active and L evaluated, known at compile time
+    const bool withL = SWZ ? true : (A.withL != 0);
+    auto act = [&](int d) { return SWZ ? true : (G.act[d] != 0); };
     int c[3];
     double Lz[NQ];
     if constexpr (SWZ == 1) {
@@ -1084,7 +1088,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     const double ps2 = ps * ps, ps4 = ps2 * ps2, ps6 = ps4 * ps2;
     const double ips6 = MET ? frcp(ps6) : 1.0, ips2 = MET ? frcp(ps2) : 1.0;
     double Lc[NQ];
-    if (A.withL) {
+    if (withL) {
 #pragma unroll
         for (int v = 0; v < NQ; v++) Lc[v] = SWZ ? ldb(io.Lxy[v], o) + Lz[v] : ldb(io.Lxy[v], o);
         double rho = ldb(io.spm[0], o), pr = ldb(io.spm[4], o);
@@ -1096,7 +1100,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         double divqE = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            if (!G.act[d]) continue;
+            if (!act(d)) continue;
             unsigned sd = (unsigned)G.st[d] << 3;
             double qp = ldb(io.spm[5 + d], o + sd), qm = ldb(io.spm[5 + d], o - sd);
             if (MET) {
@@ -1118,7 +1122,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
             const double Psic = ldb(io.spm[8], o), Phic = ldb(io.spm[9], o);
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                if (!G.act[d]) continue;
+                if (!act(d)) continue;
                 unsigned sd = (unsigned)G.st[d] << 3;
                 double dPsi = (ldb(io.spm[8], o + sd) - ldb(io.spm[8], o - sd)) * (0.5 * G.idx[d]);
                 double dPhi = (ldb(io.spm[9], o + sd) - ldb(io.spm[9], o - sd)) * (0.5 * G.idx[d]);
@@ -1133,7 +1137,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
 #pragma unroll
             for (int i = 0; i < 3; i++) {
                 E[i] = ps2 * ldb(io.spm[5 + i], o);
-                B[i] = ps2 * bcc_dev<MET, GLM>(G, io.sfm, ips6, o, i);
+                B[i] = ps2 * bcc_dev<MET, GLM, SWZ == 1>(G, io.sfm, ips6, o, i);
             }
             double w = (rho + P.G1 * pr) * W * W;
             double U = 0.5 * (E[0] * E[0] + E[1] * E[1] + E[2] * E[2] + B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
@@ -1144,7 +1148,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
             double sdt = 0.0, ips = frcp(ps);
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                if (!G.act[d]) continue;
+                if (!act(d)) continue;
                 unsigned sd = (unsigned)G.st[d] << 3;
                 double da = (ldb(io.met[0], o + sd) - ldb(io.met[0], o - sd)) * (0.5 * G.idx[d]);
                 double dp = (ldb(io.met[1], o + sd) - ldb(io.met[1], o - sd)) * (0.5 * G.idx[d]);
@@ -1174,12 +1178,23 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         qs[11] = ldb(io.q[8], o);
         qs[12] = ldb(io.q[9], o);
     }
+    // the stored R slots this pass reads: loaded before the first is used
+    // (the conditions are uniform over the launch); the stored L slots, eight
+    // values each, are loaded per stage to bound the live registers
+    double rv[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        if (j < A.p && A.cR[j] != 0.0) {
+#pragma unroll
+            for (int i = 0; i < 3; i++) rv[j][i] = ldb(io.Rj[j][i], o);
+        }
+    }
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         if (j >= A.p) continue;
         if (A.cL[j] != 0.0) {
             double w = A.dt * A.cL[j];
-            if (A.withL && j == A.p - 1) {
+            if (withL && j == A.p - 1) {
 #pragma unroll
                 for (int v = 0; v < NQ; v++) qs[v] += w * Lc[v];
             } else {
@@ -1195,9 +1210,8 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
             double w = A.dt * A.cR[j];
 #pragma unroll
             for (int i = 0; i < 3; i++) {
-                const double r = ldb(io.Rj[j][i], o);
-                qs[5 + i] += w * r;
-                if (A.foldR) Rfold[i] += A.fR[j] * r;
+                qs[5 + i] += w * rv[j][i];
+                if (A.foldR) Rfold[i] += A.fR[j] * rv[j][i];
             }
         }
     }
@@ -1225,7 +1239,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < 3; i++) B[i] = ps2 * bcc_dev<MET>(G, io.sfp, ips6, o, i);
+        for (int i = 0; i < 3; i++) B[i] = ps2 * bcc_dev<MET, false, SWZ == 1>(G, io.sfp, ips6, o, i);
     }
     const double ips8 = ips6 * ips2;
     double D = qs[0] * ips6, tau = qs[4] * ips6;
