@@ -598,10 +598,19 @@ __device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
 
     const int tid = threadIdx.x;
     const int org[3] = {R.lo[0] + (int)blk.x * T0, R.lo[1] + (int)blk.y * T1, R.lo[2] + (int)blk.z * T2};
-    const bool actA = !ct_flat<F>(A) && G.act[A], actB = !ct_flat<F>(B) && G.act[B];
+    // the forms are chosen from the grid's activity: in each of them every
+    // direction that is not flat by the form is active
+    constexpr bool actA = !ct_flat<F>(A), actB = !ct_flat<F>(B);
 
-    // ---- step 1: a-face states of psi^4 E_k and q_B^a, clamped into range
-    for (int l = tid; l < NL; l += kBlock) {
+    // ---- step 1: a-face states of psi^4 E_k and q_B^a, clamped into range;
+    // a lane's loads of all its rounds are issued before the first use (lanes
+    // past the end of the last round repeat its last point and store nothing)
+    constexpr int NR = (NL + kBlock - 1) / kBlock;
+    double wE[NR][6], wP[NR][2], wQ[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        int l = tid + r * kBlock;
+        if (r == NR - 1 && NL % kBlock != 0) l = l < NL ? l : NL - 1;
         int e[3] = {l % E0, (l / E0) % E1, l / (E0 * E1)};
         int c[3];
 #pragma unroll
@@ -615,20 +624,42 @@ __device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
             }
             c[d] = c[d] < lo ? lo : (c[d] > hi ? hi : c[d]);
         }
-        int id = lin(G, c);
-        unsigned o = (unsigned)id << 3;
-        double al, ps;
-        face_metric<MET>(G, met, o, A, al, ps);
-        double p4 = MET ? ps * ps * ps * ps : 1.0;
-        double L, Rv;
+        const unsigned o = (unsigned)lin(G, c) << 3, sa = (unsigned)G.st[A] << 3;
         if (actA) {
-            recon_at<REC>(Ek, id, G.st[A], L, Rv);
+#pragma unroll
+            for (int m = 0; m < 6; m++) {
+                // minmod and MC use the four middle points (the outer two are copies)
+                const int mm = REC == GR_PPM ? m : (m == 0 ? 1 : (m == 5 ? 4 : m));
+                wE[r][m] = ldb(Ek, o + (unsigned)(mm - 3) * sa);
+            }
         } else {
-            L = Rv = ldb(Ek, o);
+            wE[r][0] = ldb(Ek, o);
         }
-        sEL[l] = p4 * L;
-        sER[l] = p4 * Rv;
-        sQa[l] = ldb(sf.p[A], o);
+        if (MET) {
+            wP[r][1] = ldb(met.p[1], o);
+            wP[r][0] = actA ? ldb(met.p[1], o - sa) : wP[r][1];
+        }
+        wQ[r] = ldb(sf.p[A], o);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const int l = tid + r * kBlock;
+        if (l < NL) {
+            double p4 = 1.0;
+            if (MET) {
+                const double ps = actA ? 0.5 * (wP[r][0] + wP[r][1]) : wP[r][1];
+                p4 = ps * ps * ps * ps;
+            }
+            double L, Rv;
+            if (actA) {
+                recon_face<REC>(wE[r], L, Rv);
+            } else {
+                L = Rv = wE[r][0];
+            }
+            sEL[l] = p4 * L;
+            sER[l] = p4 * Rv;
+            sQa[l] = wQ[r];
+        }
     }
     __syncthreads();
 
@@ -772,7 +803,7 @@ __device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
 
     const int org[3] = {R.lo[0] + (int)blk.x * CtTile<K>::T[0], R.lo[1] + (int)blk.y * CtTile<K>::T[1],
                         R.lo[2] + (int)blk.z * CtTile<K>::T[2]};
-    const bool actA = G.act[A], actB = G.act[B];
+    constexpr bool actA = true, actB = true;  // the box form runs where both are active
     {
         CtRegs<BE> rE;
         CtRegs<BQa> rQa;
