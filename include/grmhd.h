@@ -11,9 +11,17 @@
  *
  * Layouts (shared with the caller):
  *   - cell arrays have N_d = n_d + 2 ng points per active direction (1 for an
- *     inactive one), x fastest: index i + Nx (j + Ny k).  A "field block"
- *     holds F such arrays back to back, field f starting at f * stride with
- *     stride = gr_field_stride(grid) doubles (>= Nx Ny Nz, 256-byte aligned);
+ *     inactive one), x fastest, rows padded: point (i,j,k) of a field sits at
+ *     index o + i + P (j + Ny k) from the field's start, with row stride
+ *     P = gr_row_stride(grid) (Nx rounded up to 16 doubles, one 128-byte line)
+ *     and origin o = gr_field_origin(grid) (< 16), chosen so that the first
+ *     interior point of every row (i = ng) starts a 128-byte line when the
+ *     field starts on one.  The padding points are never read or written.  A
+ *     "field block" holds F such arrays back to back, field f starting at
+ *     f * stride with stride = gr_field_stride(grid) doubles
+ *     (>= o + P Ny Nz, a multiple of 32); allocate blocks 256-byte aligned.
+ *     Host arrays passed to gr_init_state are compact instead: index
+ *     i + Nx (j + Ny k), fields back to back;
  *   - q: 8 fields, the densitised conserved variables of Sec 2.1,
  *     (q_D, q_S_x, q_S_y, q_S_z, q_tau, q_E^x, q_E^y, q_E^z), q = psi^6 (...);
  *   - face: 3 fields, face-centred q_B^d = psi^6 B^d (Sec 3.2); field d at
@@ -42,7 +50,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 4
+#define GR_ABI_VERSION 5
 
 typedef enum {
     GR_OK = 0,
@@ -104,6 +112,14 @@ gr_status gr_validate(const gr_grid *grid);
 /* Doubles between consecutive fields of a field block. */
 size_t gr_field_stride(const gr_grid *grid);
 
+/* Doubles between consecutive rows (j to j + 1) of a device cell array; rows
+ * are Nx points padded to a multiple of 16.  0 for an invalid grid. */
+size_t gr_row_stride(const gr_grid *grid);
+
+/* Doubles from the start of a device field to its point (0, 0, 0).  0 for
+ * an invalid grid (also a valid origin: check gr_validate first). */
+size_t gr_field_origin(const gr_grid *grid);
+
 /* Bytes of workspace the stage calls need (stage states, stored L and R
  * terms of the IMEX tableau, scratch, counters). */
 size_t gr_workspace_bytes(const gr_grid *grid);
@@ -121,8 +137,9 @@ gr_status gr_workspace_offset(const gr_grid *grid, int kind, int stage, int fiel
  * NULL), plus face_host (3 cell-sized arrays, densitised, or NULL); q_E =
  * psi^6 E everywhere; D, S, tau from the primitives on interior cells.
  * prim_host: 5 cell arrays, E_host: 3 cell arrays, metric_host: 2 cell arrays
- * (alpha, psi) or NULL; all with the cell-array layout above (contiguous,
- * stride Nx Ny Nz between fields).  Also resets the failure counter and fills
+ * (alpha, psi) or NULL; all host arrays are compact (index i + Nx (j + Ny k),
+ * stride Nx Ny Nz between fields) and are copied into the padded device
+ * layout.  Also resets the failure counter and fills
  * the ghost points of the workspace stage storage.  With glm the face
  * fields are then turned into the cell-centred q_B^d (mean of the cell's two
  * d-faces; the face value itself along an inactive direction and at the last

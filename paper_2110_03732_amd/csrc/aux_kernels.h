@@ -11,13 +11,18 @@ struct FlatBox {
     int lo[3], cnt[3];
     long total;
 };
+__device__ __forceinline__ void flat_coords(const FlatBox &R, long t, int c[3])
+{
+    c[0] = R.lo[0] + (int)(t % R.cnt[0]);
+    long r = t / R.cnt[0];
+    c[1] = R.lo[1] + (int)(r % R.cnt[1]);
+    c[2] = R.lo[2] + (int)(r / R.cnt[1]);
+}
 __device__ __forceinline__ int flat_point(const Geo &G, const FlatBox &R, long t)
 {
-    int c0 = R.lo[0] + (int)(t % R.cnt[0]);
-    long r = t / R.cnt[0];
-    int c1 = R.lo[1] + (int)(r % R.cnt[1]);
-    int c2 = R.lo[2] + (int)(r / R.cnt[1]);
-    return c0 + G.st[1] * c1 + G.st[2] * c2;
+    int c[3];
+    flat_coords(R, t, c);
+    return lin(G, c);
 }
 
 // Sec 4: face fields q_B^d = d_{m1} A_{m2} - d_{m2} A_{m1} from the edge
@@ -32,6 +37,7 @@ __global__ void __launch_bounds__(256) k_curlA(Geo G, int Ne0, int Ne1, const do
     c[0] = tt - c[1] * G.N[0];
     c[2] = blockIdx.y;
     int t = lin(G, c);
+    long tc = c[0] + (long)G.N[0] * (c[1] + (long)G.N[1] * c[2]);  // the added field is compact
     long ie = c[0] + (long)Ne0 * (c[1] + (long)Ne1 * c[2]);
     long est[3] = {1, Ne0, (long)Ne0 * Ne1};
 #pragma unroll
@@ -42,7 +48,7 @@ __global__ void __launch_bounds__(256) k_curlA(Geo G, int Ne0, int Ne1, const do
             if (G.act[m1]) s += (A[m2 * es + ie + est[m1]] - A[m2 * es + ie]) * G.idx[m1];
             if (G.act[m2]) s -= (A[m1 * es + ie + est[m2]] - A[m1 * es + ie]) * G.idx[m2];
         }
-        face.p[d][t] = fadd ? fadd[d * np + t] + s : s;
+        face.p[d][t] = fadd ? fadd[d * np + tc] + s : s;
     }
 }
 
@@ -191,11 +197,9 @@ __global__ void __launch_bounds__(256) k_divb_cc_partial(Geo G, FlatBox R, BcArg
 {
     double a = 0.0, b = 0.0, c = 0.0;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < R.total; t += (long)gridDim.x * blockDim.x) {
-        int id = flat_point(G, R, t);
         int p[3];
-        p[2] = id / G.st[2];
-        p[1] = (id - p[2] * G.st[2]) / G.st[1];
-        p[0] = id - p[2] * G.st[2] - p[1] * G.st[1];
+        flat_coords(R, t, p);
+        const int id = lin(G, p);
         double dv = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; d++) {

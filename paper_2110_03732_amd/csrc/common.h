@@ -10,7 +10,8 @@ namespace gr {
 
 struct Geo {
     int N[3], g[3], n[3], act[3];
-    int st[3];   // index stride per direction: 1, Nx, Nx Ny
+    int st[3];   // index stride per direction: 1, row stride P, P Ny
+    int o;       // offset of point (0, 0, 0) from the start of its field
     long fs;     // field stride (doubles) of a field block
     double dx[3], idx[3];
 };
@@ -97,7 +98,10 @@ __device__ __forceinline__ bool region_point(const Region &R, const Blk &b, int 
     return true;
 }
 
-__device__ __forceinline__ int lin(const Geo &G, const int c[3]) { return c[0] + G.st[1] * c[1] + G.st[2] * c[2]; }
+__device__ __forceinline__ int lin(const Geo &G, const int c[3])
+{
+    return G.o + c[0] + G.st[1] * c[1] + G.st[2] * c[2];
+}
 
 // loads / stores at a 32-bit byte offset from a uniform base pointer: the
 // address is formed by the memory instruction (scalar base + vector offset)

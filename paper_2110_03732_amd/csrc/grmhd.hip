@@ -76,6 +76,10 @@ struct TScope {
 };
 
 // ---------------------------------------------------------------------------
+// field layout: 16 doubles = one 128-byte line; fields start 256-byte aligned
+int row_stride(int nx) { return (nx + 15) / 16 * 16; }
+int field_origin(int ng) { return (16 - ng % 16) % 16; }
+
 Geo make_geo(const gr_grid *g)
 {
     Geo G;
@@ -87,10 +91,13 @@ Geo make_geo(const gr_grid *g)
         G.dx[d] = G.act[d] ? (g->hi[d] - g->lo[d]) / g->n[d] : 1.0;
         G.idx[d] = 1.0 / G.dx[d];
     }
+    // rows padded to whole 128-byte lines and the first interior point of
+    // every row on a line boundary: a tile row of 16 cells is one line
     G.st[0] = 1;
-    G.st[1] = G.N[0];
-    G.st[2] = G.N[0] * G.N[1];
-    long np = (long)G.N[0] * G.N[1] * G.N[2];
+    G.st[1] = row_stride(G.N[0]);
+    G.st[2] = G.st[1] * G.N[1];
+    G.o = field_origin(G.g[0]);
+    long np = G.o + (long)G.st[2] * G.N[2];
     G.fs = (np + 31) / 32 * 32;
     return G;
 }
@@ -1352,8 +1359,9 @@ gr_status gr_validate(const gr_grid *g)
     if (!(g->rho_atm > 0.0) || !(g->p_atm >= 0.0) || !(g->atm_factor >= 1.0)) return GR_EINVAL;
     if (g->metric != 0 && g->metric != 1) return GR_EINVAL;
     // 32-bit indices inside a field; the z extent is a launch-grid dimension
-    double cells = 1.0;
-    for (int d = 0; d < 3; d++) cells *= (d < g->ndim) ? (g->n[d] + 2.0 * g->ng) : 1.0;
+    double cells = row_stride(g->n[0] + 2 * g->ng);  // padded rows
+    for (int d = 1; d < 3; d++) cells *= (d < g->ndim) ? (g->n[d] + 2.0 * g->ng) : 1.0;
+    cells += field_origin(g->ng);
     if (cells > 5.0e8) return GR_EINVAL;  // byte offsets inside a field stay below 2^32
     if (g->ndim == 3 && g->n[2] + 2 * g->ng > 65535) return GR_EINVAL;
     return GR_OK;
@@ -1363,6 +1371,18 @@ size_t gr_field_stride(const gr_grid *g)
 {
     if (gr_validate(g) != GR_OK) return 0;
     return (size_t)make_geo(g).fs;
+}
+
+size_t gr_row_stride(const gr_grid *g)
+{
+    if (gr_validate(g) != GR_OK) return 0;
+    return (size_t)make_geo(g).st[1];
+}
+
+size_t gr_field_origin(const gr_grid *g)
+{
+    if (gr_validate(g) != GR_OK) return 0;
+    return (size_t)make_geo(g).o;
 }
 
 size_t gr_workspace_bytes(const gr_grid *g)
@@ -1407,16 +1427,19 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     Layout Ly = layout(g);
     long np = (long)G.N[0] * G.N[1] * G.N[2];
     size_t cb = (size_t)np * sizeof(double);
+    // host fields are compact (rows of Nx points): copied row by row into the
+    // padded rows of the device layout
+    auto put = [&](double *field, const double *host) {
+        return hipMemcpy2DAsync(field + G.o, (size_t)G.st[1] * sizeof(double), host, (size_t)G.N[0] * sizeof(double),
+                                (size_t)G.N[0] * sizeof(double), (size_t)G.N[1] * G.N[2], hipMemcpyHostToDevice, s);
+    };
     HIPCHK(hipMemsetAsync(st->work, 0, kHeader, s));
-    for (int v5 = 0; v5 < 5; v5++)
-        HIPCHK(hipMemcpyAsync(st->prim + v5 * G.fs, prim_host + (size_t)v5 * np, cb, hipMemcpyHostToDevice, s));
+    for (int v5 = 0; v5 < 5; v5++) HIPCHK(put(st->prim + v5 * G.fs, prim_host + (size_t)v5 * np));
     if (g->metric)
-        for (int v2 = 0; v2 < 2; v2++)
-            HIPCHK(hipMemcpyAsync(st->metric + v2 * G.fs, metric_host + (size_t)v2 * np, cb, hipMemcpyHostToDevice, s));
+        for (int v2 = 0; v2 < 2; v2++) HIPCHK(put(st->metric + v2 * G.fs, metric_host + (size_t)v2 * np));
     // E staged in the first stage block, then q_E = psi^6 E
     double *sp0 = wfield(st, G, Ly.sprim);
-    for (int i = 0; i < 3; i++)
-        HIPCHK(hipMemcpyAsync(sp0 + i * G.fs, E_host + (size_t)i * np, cb, hipMemcpyHostToDevice, s));
+    for (int i = 0; i < 3; i++) HIPCHK(put(sp0 + i * G.fs, E_host + (size_t)i * np));
     Region Rall = region(G, 0, 7);
     dim3 gr, bl;
     launch_dims(Rall, gr, bl);

@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgrmhd.so")
 
 GR_OK, GR_EINVAL, GR_ENOMEM, GR_EHIP, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
-EXPORTED = ["gr_abi_version", "gr_strerror", "gr_validate", "gr_field_stride", "gr_workspace_bytes",
+EXPORTED = ["gr_abi_version", "gr_strerror", "gr_validate", "gr_field_stride", "gr_row_stride", "gr_field_origin",
+            "gr_workspace_bytes",
             "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim", "gr_divB_norm",
             "gr_cfl_dt", "gr_fail_count", "gr_timing_start", "gr_timing_read", "gr_kernel_class_name",
             "gr_clean_divB", "gr_batch_create", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run", "gr_batch_stats", "gr_batch_tiles",
@@ -62,6 +63,10 @@ def lib():
         L.gr_validate.argtypes = [G]
         L.gr_field_stride.argtypes = [G]
         L.gr_field_stride.restype = ctypes.c_size_t
+        L.gr_row_stride.argtypes = [G]
+        L.gr_row_stride.restype = ctypes.c_size_t
+        L.gr_field_origin.argtypes = [G]
+        L.gr_field_origin.restype = ctypes.c_size_t
         L.gr_workspace_bytes.argtypes = [G]
         L.gr_workspace_bytes.restype = ctypes.c_size_t
         L.gr_workspace_offset.argtypes = [G, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
@@ -115,6 +120,14 @@ def gr_validate(grid):
 
 def gr_field_stride(grid):
     return lib().gr_field_stride(ctypes.byref(grid))
+
+
+def gr_row_stride(grid):
+    return lib().gr_row_stride(ctypes.byref(grid))
+
+
+def gr_field_origin(grid):
+    return lib().gr_field_origin(ctypes.byref(grid))
 
 
 def gr_workspace_bytes(grid):
@@ -281,6 +294,8 @@ class Run:
         _chk(r)
         self.fs = gr_field_stride(self.grid)
         self.np = int(np.prod(setup.shape))
+        self.pitch = gr_row_stride(self.grid)  # padded device rows
+        self.origin = gr_field_origin(self.grid)
         dev = torch.device(device)
         self.nq = 10 if setup.glm else 8
         self.q = torch.zeros(self.nq * self.fs, dtype=torch.float64, device=dev)
@@ -339,10 +354,21 @@ class Run:
         return gr_fail_count(self.grid, self.state, self.stream.cuda_stream)
 
     # --- views (host copies) ------------------------------------------------
+    def offset(self, i, j, k):
+        """index of point (i, j, k) inside a device field (padded rows)"""
+        Nz, Ny, Nx = self.setup.shape
+        return self.origin + i + self.pitch * (j + Ny * k)
+
+    def _unpad(self, a):
+        """device field values (..., fs) -> compact (..., Nz, Ny, Nx)"""
+        Nz, Ny, Nx = self.setup.shape
+        lead = a.shape[:-1]
+        a = a[..., self.origin: self.origin + self.pitch * Ny * Nz].reshape(lead + (Nz, Ny, self.pitch))
+        return np.ascontiguousarray(a[..., :Nx])
+
     def _block(self, t, nf):
         self.stream.synchronize()
-        a = t.view(nf, self.fs)[:, : self.np].cpu().numpy()
-        return a.reshape((nf,) + self.setup.shape)
+        return self._unpad(t.view(nf, self.fs).cpu().numpy())
 
     def prims(self):
         return self._block(self.prim, 5)
@@ -361,7 +387,7 @@ class Run:
     def work_field(self, kind, stage, field):
         off = gr_workspace_offset(self.grid, kind, stage, field) // 8
         self.stream.synchronize()
-        return self.work[off: off + self.np].cpu().numpy().reshape(self.setup.shape)
+        return self._unpad(self.work[off: off + self.fs].cpu().numpy())
 
 
 class Batch:

@@ -107,7 +107,8 @@ int main(int argc, char **argv)
     double *out = malloc(5 * (size_t)g.n[0] * sizeof(double));
     if (!out) return 1;
     for (int v = 0; v < 5; v++)
-        HCHECK(hipMemcpy(out + (size_t)v * g.n[0], s.prim + (size_t)v * fs + g.ng, g.n[0] * sizeof(double),
+        HCHECK(hipMemcpy(out + (size_t)v * g.n[0], s.prim + (size_t)v * fs + gr_field_origin(&g) + g.ng,
+                         g.n[0] * sizeof(double),
                          hipMemcpyDeviceToHost));
     int ok = fails == 0 && div[2] <= 1e-12;
     for (int i = 0; i < 5 * g.n[0]; i++) ok = ok && isfinite(out[i]);

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     L = grmhd.lib()
     for name in declared_symbols():
         assert hasattr(L, name), name
-    assert grmhd.gr_abi_version() == 4
+    assert grmhd.gr_abi_version() == 5
 
 
 def test_validation_rejects_bad_grids():
@@ -77,13 +77,14 @@ def test_validation_rejects_bad_grids():
 
 
 def test_validation_size_limits():
-    """a field must stay below 2^32 bytes (32-bit offsets: at most 5e8 padded
-    points) and the padded z extent is a launch-grid dimension (<= 65535)"""
+    """a field must stay below 2^32 bytes (32-bit offsets: at most 5e8 points
+    with padded rows) and the padded z extent is a launch-grid dimension
+    (<= 65535)"""
     s = W.tov_star(16)
     g = grmhd.grid_of(s)
     for n, ok in [((780, 780, 780), True), ((800, 800, 800), False), ((4, 4, 65529), True), ((4, 4, 65530), False)]:
         g.n[0], g.n[1], g.n[2] = n
-        pts = (n[0] + 2 * g.ng) * (n[1] + 2 * g.ng) * (n[2] + 2 * g.ng)
+        pts = (n[0] + 2 * g.ng + 15) // 16 * 16 * (n[1] + 2 * g.ng) * (n[2] + 2 * g.ng) + (16 - g.ng % 16) % 16
         assert (pts <= 5e8 and n[2] + 2 * g.ng <= 65535) == ok
         assert (grmhd.gr_validate(g) == 0) == ok, n
     g.n[0] = g.n[1] = g.n[2] = 0
@@ -97,6 +98,13 @@ def test_layout(make):
     g = grmhd.grid_of(s)
     fs = grmhd.gr_field_stride(g)
     assert fs >= s.shape[0] * s.shape[1] * s.shape[2] and fs % 32 == 0
+    # padded rows: whole 128-byte lines, the first interior point of every
+    # row on a line boundary, everything inside the field
+    Nz, Ny, Nx = s.shape
+    P, o = grmhd.gr_row_stride(g), grmhd.gr_field_origin(g)
+    assert P % 16 == 0 and Nx <= P < Nx + 16
+    assert 0 <= o < 16 and (o + s.ng) % 16 == 0
+    assert o + P * Ny * Nz <= fs
     wb = grmhd.gr_workspace_bytes(g)
     nst = 2 if s.imex == W.SSP2 else 4
     # stage prims + E (+ Psi, Phi with GLM), stage faces, stored L (+ q_B,

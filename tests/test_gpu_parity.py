@@ -322,16 +322,16 @@ def test_failure_fallback_counted():
     s = W.random_states((8, 8, 8), seed=7)
     run = gpu_run(s)
     q = run.q.view(8, run.fs)
-    idx = [s.g(0) + 1 + s.shape[2] * (s.g(1) + 2 + s.shape[1] * (s.g(2) + 3)),
-           s.g(0) + 4 + s.shape[2] * (s.g(1) + 5 + s.shape[1] * (s.g(2) + 1))]
-    for i in idx:
-        q[4, i] = -1.0
+    pts = [(s.g(0) + 1, s.g(1) + 2, s.g(2) + 3), (s.g(0) + 4, s.g(1) + 5, s.g(2) + 1)]
+    for i, j, k in pts:
+        q[4, run.offset(i, j, k)] = -1.0
     torch.cuda.synchronize()
     run.con2prim()
     assert run.fail_count() == 2
-    p = run.prims().reshape(5, -1)
-    for i in idx:
-        assert p[0, i] == s.rho_atm and p[4, i] == s.p_atm and np.all(p[1:4, i] == 0.0)
+    p = run.prims()
+    for i, j, k in pts:
+        c = p[:, k, j, i]
+        assert c[0] == s.rho_atm and c[4] == s.p_atm and np.all(c[1:4] == 0.0)
 
 
 def test_bitwise_deterministic():
