@@ -52,6 +52,19 @@ __global__ void __launch_bounds__(256) k_curlA(Geo G, int Ne0, int Ne1, const do
     }
 }
 
+// a compact field (index i + Nx (j + Ny k), as the host passes it) into the
+// padded device layout; every padded point
+__global__ void __launch_bounds__(256) k_unpack(Geo G, const double *__restrict__ src, double *__restrict__ dst)
+{
+    int c[3];
+    int tt = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tt >= G.N[0] * G.N[1]) return;
+    c[1] = tt / G.N[0];
+    c[0] = tt - c[1] * G.N[0];
+    c[2] = blockIdx.y;
+    dst[lin(G, c)] = src[c[0] + (long)G.N[0] * (c[1] + (long)G.N[1] * c[2])];
+}
+
 // conserved D, S, tau of the interior cells from primitives, E and faces
 template <int MET>
 __global__ void __launch_bounds__(256) k_init_cons(Geo G, Phys P, Region R, CPtr<5> prim, CPtr<3> E, CPtr<3> face,

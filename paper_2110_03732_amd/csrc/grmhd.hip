@@ -1427,22 +1427,29 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     Layout Ly = layout(g);
     long np = (long)G.N[0] * G.N[1] * G.N[2];
     size_t cb = (size_t)np * sizeof(double);
-    // host fields are compact (rows of Nx points): copied row by row into the
-    // padded rows of the device layout
-    auto put = [&](double *field, const double *host) {
-        return hipMemcpy2DAsync(field + G.o, (size_t)G.st[1] * sizeof(double), host, (size_t)G.N[0] * sizeof(double),
-                                (size_t)G.N[0] * sizeof(double), (size_t)G.N[1] * G.N[2], hipMemcpyHostToDevice, s);
-    };
-    HIPCHK(hipMemsetAsync(st->work, 0, kHeader, s));
-    for (int v5 = 0; v5 < 5; v5++) HIPCHK(put(st->prim + v5 * G.fs, prim_host + (size_t)v5 * np));
-    if (g->metric)
-        for (int v2 = 0; v2 < 2; v2++) HIPCHK(put(st->metric + v2 * G.fs, metric_host + (size_t)v2 * np));
-    // E staged in the first stage block, then q_E = psi^6 E
-    double *sp0 = wfield(st, G, Ly.sprim);
-    for (int i = 0; i < 3; i++) HIPCHK(put(sp0 + i * G.fs, E_host + (size_t)i * np));
     Region Rall = region(G, 0, 7);
     dim3 gr, bl;
     launch_dims(Rall, gr, bl);
+    double *scratch = wfield(st, G, Ly.L);  // the stored-L block (>= 22 fields) is free before the first step
+    // host fields are compact: one contiguous copy into scratch, then spread
+    // into the padded rows of the device layout
+    auto put = [&](double *field, const double *host) -> gr_status {
+        HIPCHK(hipMemcpyAsync(scratch, host, cb, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_unpack, gr, bl, 0, s, G, scratch, field);
+        LAUNCHCHK();
+        return GR_OK;
+    };
+    HIPCHK(hipMemsetAsync(st->work, 0, kHeader, s));
+    gr_status e;
+    for (int v5 = 0; v5 < 5; v5++)
+        if ((e = put(st->prim + v5 * G.fs, prim_host + (size_t)v5 * np)) != GR_OK) return e;
+    if (g->metric)
+        for (int v2 = 0; v2 < 2; v2++)
+            if ((e = put(st->metric + v2 * G.fs, metric_host + (size_t)v2 * np)) != GR_OK) return e;
+    // E staged in the first stage block, then q_E = psi^6 E
+    double *sp0 = wfield(st, G, Ly.sprim);
+    for (int i = 0; i < 3; i++)
+        if ((e = put(sp0 + i * G.fs, E_host + (size_t)i * np)) != GR_OK) return e;
     hipLaunchKernelGGL(k_init_qE, gr, bl, 0, s, G, g->metric, cptrs<3>(sp0, G.fs), cptrs<2>(st->metric, G.fs),
                        ptrs<8>(st->q, G.fs));
     LAUNCHCHK();
@@ -1450,7 +1457,6 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     int Ne0 = G.N[0] + (G.act[0] ? 1 : 0), Ne1 = G.N[1] + (G.act[1] ? 1 : 0), Ne2 = G.N[2] + (G.act[2] ? 1 : 0);
     long es = (long)Ne0 * Ne1 * Ne2;
     double *Ad = nullptr, *fd = nullptr;
-    double *scratch = wfield(st, G, Ly.L);  // the stored-L block (>= 22 fields) is free before the first step
     if (A_host) {
         if ((size_t)3 * es > (size_t)12 * G.fs) return GR_EINVAL;
         Ad = scratch;
