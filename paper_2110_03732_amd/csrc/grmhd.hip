@@ -725,6 +725,7 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     }
     // cells
     CellArgs &c = pl.ca;
+    std::memset(&c, 0, sizeof(c));  // no paired stage unless run_pair sets one
     c.G = G;
     c.P = P;
     c.A = A;
@@ -816,8 +817,16 @@ void launch_cell(const Variant &V, int swz, const CellArgs &a, hipStream_t s)
         auto go = [&](auto X, auto GL) {
             constexpr bool x = decltype(X)::value != 0, gl = decltype(GL)::value != 0;
             if (!swz) {
-                if constexpr (cell_compiled<x, gl, 1, 1>())
+                if constexpr (cell_compiled<x, gl, 1, 1>()) {
+                    if constexpr (!gl) {
+                        if (a.pair) {
+                            hipLaunchKernelGGL((k_cell_update<r, m, 0, 1, 1, x, false, true>), d3(a.gd), dim3(kBlock), 0,
+                                               s, a);
+                            return;
+                        }
+                    }
                     hipLaunchKernelGGL((k_cell_update<r, m, 0, 1, 1, x, gl>), d3(a.gd), dim3(kBlock), 0, s, a);
+                }
                 return;
             }
             with_cz(V.cz, [&](auto TX, auto TZ) {
@@ -870,6 +879,40 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
     gr_status r = plan_pass(g, st, p, dt, V, pl);
     if (r != GR_OK) return r;
     return launch_plan(V, pl, s);
+}
+
+// Passes 0 and 1 of a whole step can run as one point-wise launch when L of
+// stage 0 is never used and stage 1 has no explicit term but a_10 R_0 (its
+// faces are those of time level n): IMEX-SSP3(4,3,3).  Stage 0's primitives
+// are then kept in registers (they only seed stage 1's Newton guess).  Not
+// for GLM (stage q_B blocks), frozen matter, or when pass 1 folds stored
+// sums (the last implicit pass).
+bool pairable(const gr_grid *g)
+{
+    const Tableau T = tableau(g->imex);
+    if (g->glm || g->frozen_matter || T.s < 3) return false;
+    if (needL(T, 0) || !faces_are_n(T, 1)) return false;
+    return !foldR_applies(T) || T.s - 1 != 1;
+}
+gr_status run_pair(const gr_grid *g, gr_state *st, double dt, hipStream_t s)
+{
+    Variant V = default_variant(g);
+    PassPlan p0, p1;
+    gr_status r = plan_pass(g, st, 0, dt, V, p0);
+    if (r != GR_OK) return r;
+    r = plan_pass(g, st, 1, dt, V, p1);
+    if (r != GR_OK) return r;
+    if (p0.xy || p0.face || p0.swz || p1.xy || p1.face || p1.swz || p1.ca.A.storeL || p1.ca.A.foldR)
+        return GR_EUNSUPPORTED;  // not point-wise: the caller runs the passes one by one
+    CellArgs &c = p0.ca;
+    c.pair = 1;
+    c.A2 = p1.ca.A;
+    for (int v = 0; v < 8; v++) c.out2[v] = p1.ca.io.out[v];
+    for (int i = 0; i < 3; i++) c.Rout2[i] = p1.ca.io.Rout[i];
+    // q, faces, metric and guess read once; R_0, stage 1 block and R_1 written
+    const Geo &G = c.G;
+    p0.ca_bytes = 8.0 * G.n[0] * G.n[1] * G.n[2] * (8 + 3 + (g->metric ? 2 : 0) + 3 + 3 + 8 + 3);
+    return launch_plan(V, p0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1514,9 +1557,18 @@ gr_status gr_step(const gr_grid *g, gr_state *st, double dt, hipStream_t s)
 {
     gr_status v = gr_validate(g);
     if (v != GR_OK) return v;
+    v = check_state(g, st);
+    if (v != GR_OK) return v;
+    if (!(dt > 0.0)) return GR_EINVAL;
     int ns = tableau(g->imex).s;
-    for (int p = 0; p <= ns; p++) {
-        v = gr_imex_stage(g, st, p, dt, s);
+    int p0 = 0;
+    if (pairable(g)) {
+        v = run_pair(g, st, dt, s);
+        if (v == GR_OK) p0 = 2;
+        else if (v != GR_EUNSUPPORTED) return v;
+    }
+    for (int p = p0; p <= ns; p++) {
+        v = run_pass(g, st, p, dt, s);
         if (v != GR_OK) return v;
     }
     return GR_OK;
@@ -1546,6 +1598,7 @@ gr_status gr_con2prim(const gr_grid *g, gr_state *st, hipStream_t s)
     io.met[1] = st->metric ? st->metric + G.fs : nullptr;
     io.nfail = wcounter(st);
     CellArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
     ca.G = G;
     ca.P = P;
     ca.R = region(G, 0);

@@ -1072,8 +1072,14 @@ struct CellArgs {
     StageArgs A;
     CellIO io;
     GridDims gd;
+    // paired launch (point-wise passes p and p + 1, the PAIR instances):
+    // stage p + 1's weights and outputs; stage p's primitives are not stored
+    int pair;
+    StageArgs A2;
+    double *out2[8];
+    double *Rout2[3];
 };
-template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM, bool PAIR = false>
 __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
 {
     const Geo &G = args.G;
@@ -1319,57 +1325,100 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         return;
     }
     if (!A.fin) {
-        double eta = cell_eta(P, D);
-        if (D <= P.D_atm) {
-            status = 1;
-        } else {
-            ImpSys sy;
-            sy.D = D;
-            sy.tau = tau;
-            sy.iG1 = P.iG1;
+        const double eta = cell_eta(P, D);
+        // one implicit stage (eq. im_E with the velocity Newton solve, Sec
+        // 2.4) from E*, the guess u (read from memory when gmem), B and
+        // D, S, tau; returns the status and the stage primitives and E
+        auto implicit_stage = [&](double aii_dt, const double Es_[3], const double *const *gmem, double u_[3],
+                                  double &rho_, double &pr_, double E_[3]) -> int {
+            int st = 0;
+            if (D <= P.D_atm) {
+                st = 1;
+            } else {
+                ImpSys sy;
+                sy.D = D;
+                sy.tau = tau;
+                sy.iG1 = P.iG1;
 #pragma unroll
-            for (int i = 0; i < 3; i++) {
-                sy.S[i] = S[i];
-                sy.Es[i] = Es[i];
-                sy.B[i] = B[i];
-                u[i] = ps2 * ldb(io.guess[1 + i], o);
+                for (int i = 0; i < 3; i++) {
+                    sy.S[i] = S[i];
+                    sy.Es[i] = Es_[i];
+                    sy.B[i] = B[i];
+                    if (gmem) u_[i] = ps2 * ldb(gmem[1 + i], o);
+                }
+                sy.B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+                sy.et = eta / (al * aii_dt);
+                sy.xi = P.xi;
+                ImpEval ev;
+                int bad = implicit_solve<XI>(sy, P.tol, P.maxit, u_, ev);
+                if (!bad) {
+                    rho_ = D * ev.iW;
+                    pr_ = (ev.wt * ev.iW - rho_) * P.iG1;
+                    if (pr_ < 0.0 && pr_ >= -1e-12 * rho_) pr_ = 0.0;  // cold-gas round-off
+                    if (!(pr_ >= 0.0) || !(ev.W <= 1e4) || !(rho_ >= P.rho_atm)) bad = 1;
+#pragma unroll
+                    for (int i = 0; i < 3; i++) E_[i] = ev.E[i];
+                }
+                if (bad) st = 2;
             }
-            sy.B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
-            sy.et = eta / (al * A.aii_dt);
-            sy.xi = P.xi;
-            ImpEval ev;
-            int bad = implicit_solve<XI>(sy, P.tol, P.maxit, u, ev);
-            if (!bad) {
-                rho = D * ev.iW;
-                pr = (ev.wt * ev.iW - rho) * P.iG1;
-                if (pr < 0.0 && pr >= -1e-12 * rho) pr = 0.0;  // cold-gas round-off
-                if (!(pr >= 0.0) || !(ev.W <= 1e4) || !(rho >= P.rho_atm)) bad = 1;
+            if (st) {
+                rho_ = P.rho_atm;
+                u_[0] = u_[1] = u_[2] = 0.0;
+                pr_ = P.p_atm;
+                // exact solution at rest: (1 + et) E = et E* + xi B, as (E* + xi B/et)/(1 + 1/et)
+                const double iet = al * aii_dt / eta;
+                const double fct = 1.0 / (1.0 + iet);
 #pragma unroll
-                for (int i = 0; i < 3; i++) E[i] = ev.E[i];
+                for (int i = 0; i < 3; i++) E_[i] = (Es_[i] + P.xi * iet * B[i]) * fct;
             }
-            if (bad) status = 2;
-        }
-        if (status) {
-            rho = P.rho_atm;
-            u[0] = u[1] = u[2] = 0.0;
-            pr = P.p_atm;
-            // exact solution at rest: (1 + et) E = et E* + xi B, as (E* + xi B/et)/(1 + 1/et)
-            const double iet = al * A.aii_dt / eta;
-            const double fct = 1.0 / (1.0 + iet);
+            return st;
+        };
+        status = implicit_stage(A.aii_dt, Es, io.guess, u, rho, pr, E);
+        static_assert(!PAIR || (SWZ == 0 && !GLM), "paired stages are point-wise, face-centred B");
+        constexpr bool pair = PAIR;
+        if (!pair) {
+            stb(io.out[0], o, rho);
 #pragma unroll
-            for (int i = 0; i < 3; i++) E[i] = (Es[i] + P.xi * iet * B[i]) * fct;
+            for (int i = 0; i < 3; i++) stb(io.out[1 + i], o, u[i] * ips2);
+            stb(io.out[4], o, pr);
         }
-        stb(io.out[0], o, rho);
-#pragma unroll
-        for (int i = 0; i < 3; i++) stb(io.out[1 + i], o, u[i] * ips2);
-        stb(io.out[4], o, pr);
-        double iadt = 1.0 / A.aii_dt;
+        const double iadt = 1.0 / A.aii_dt;
+        double Rn[3];
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             double Ec = E[i] * ips2;
-            stb(io.out[5 + i], o, Ec);
-            const double Rn = (ps6 * Ec - qs[5 + i]) * iadt;  // R = psi^6 (E - E*)/(a_ii dt)
-            stb(io.Rout[i], o, A.foldR ? Rfold[i] + A.fR[A.p] * Rn : Rn);
+            if (!pair) stb(io.out[5 + i], o, Ec);
+            Rn[i] = (ps6 * Ec - qs[5 + i]) * iadt;  // R = psi^6 (E - E*)/(a_ii dt)
+            stb(io.Rout[i], o, A.foldR ? Rfold[i] + A.fR[A.p] * Rn[i] : Rn[i]);
+        }
+        if constexpr (PAIR) {
+            {
+                // the next stage in the same launch: its only explicit term is
+                // the R just formed (no L, faces of time level n), its guess the
+                // primitives of this stage as they would have been stored
+                if (status == 2) atomicAdd(io.nfail, 1ull);
+                const StageArgs &A2 = args.A2;
+                const double w = A2.dt * A2.cR[A.p];
+                double Es2[3], u2[3], E2[3], rho2 = P.rho_atm, pr2 = P.p_atm;
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    qs[5 + i] += w * Rn[i];
+                    Es2[i] = qs[5 + i] * ips6 * ps2;
+                    u2[i] = ps2 * (u[i] * ips2);
+                }
+                status = implicit_stage(A2.aii_dt, Es2, nullptr, u2, rho2, pr2, E2);
+                stb(args.out2[0], o, rho2);
+#pragma unroll
+                for (int i = 0; i < 3; i++) stb(args.out2[1 + i], o, u2[i] * ips2);
+                stb(args.out2[4], o, pr2);
+                const double iadt2 = 1.0 / A2.aii_dt;
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    double Ec = E2[i] * ips2;
+                    stb(args.out2[5 + i], o, Ec);
+                    stb(args.Rout2[i], o, (ps6 * Ec - qs[5 + i]) * iadt2);
+                }
+            }
         }
     } else {
 #pragma unroll
@@ -1416,10 +1465,10 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     }
     if (status == 2) atomicAdd(io.nfail, 1ull);
 }
-template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM, bool PAIR = false>
 __global__ void __launch_bounds__(kBlock) k_cell_update(CellArgs a)
 {
-    cell_body<REC, MET, SWZ, TX, TZ, XI, GLM>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
+    cell_body<REC, MET, SWZ, TX, TZ, XI, GLM, PAIR>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
 }
 // the batched form reads its arguments through a pointer, which costs the
 // z-phase instance a few registers: it is held to the plain form's 3 waves per
