@@ -894,16 +894,16 @@ bool pairable(const gr_grid *g)
     if (needL(T, 0) || !faces_are_n(T, 1)) return false;
     return !foldR_applies(T) || T.s - 1 != 1;
 }
-gr_status run_pair(const gr_grid *g, gr_state *st, double dt, hipStream_t s)
+// p0: the plan of pass 0; adds pass 1 to its cell launch.  GR_EUNSUPPORTED
+// when the two passes are not both point-wise (they then run one by one).
+gr_status make_pair(const gr_grid *g, gr_state *st, double dt, const Variant &V, PassPlan &p0)
 {
-    Variant V = default_variant(g);
-    PassPlan p0, p1;
-    gr_status r = plan_pass(g, st, 0, dt, V, p0);
-    if (r != GR_OK) return r;
-    r = plan_pass(g, st, 1, dt, V, p1);
+    if (!pairable(g)) return GR_EUNSUPPORTED;
+    PassPlan p1;
+    gr_status r = plan_pass(g, st, 1, dt, V, p1);
     if (r != GR_OK) return r;
     if (p0.xy || p0.face || p0.swz || p1.xy || p1.face || p1.swz || p1.ca.A.storeL || p1.ca.A.foldR)
-        return GR_EUNSUPPORTED;  // not point-wise: the caller runs the passes one by one
+        return GR_EUNSUPPORTED;
     CellArgs &c = p0.ca;
     c.pair = 1;
     c.A2 = p1.ca.A;
@@ -912,6 +912,16 @@ gr_status run_pair(const gr_grid *g, gr_state *st, double dt, hipStream_t s)
     // q, faces, metric and guess read once; R_0, stage 1 block and R_1 written
     const Geo &G = c.G;
     p0.ca_bytes = 8.0 * G.n[0] * G.n[1] * G.n[2] * (8 + 3 + (g->metric ? 2 : 0) + 3 + 3 + 8 + 3);
+    return GR_OK;
+}
+gr_status run_pair(const gr_grid *g, gr_state *st, double dt, hipStream_t s)
+{
+    Variant V = default_variant(g);
+    PassPlan p0;
+    gr_status r = plan_pass(g, st, 0, dt, V, p0);
+    if (r != GR_OK) return r;
+    r = make_pair(g, st, dt, V, p0);
+    if (r != GR_OK) return r;
     return launch_plan(V, p0, s);
 }
 
@@ -927,6 +937,7 @@ struct BLaunch {
     int K = 0, F = 0;  // EMF launches: edge direction and kernel form
     Variant V{};
     bool swz = false;
+    bool pair = false;  // cell launches: the paired passes 0 and 1
     size_t args_off = 0, start_off = 0;  // offsets into the batch's device block
     const void *args = nullptr;
     const unsigned *start = nullptr;
@@ -997,10 +1008,30 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
     for (int p = 0; p <= b->s; p++) {
         if (p_only >= 0 && p != p_only) continue;
         std::vector<PassPlan> pl(nr);
+        // a whole step pairs passes 0 and 1 of the runs where both are point-wise
+        std::vector<char> paired(nr, 0), skip(nr, 0);
         for (int r = 0; r < nr; r++) {
             if (!use[r]) continue;
             gr_status e = plan_pass(&b->grids[r], &b->states[r], p, b->dt[r], b->var[r], pl[r]);
             if (e != GR_OK) return e;
+            if (p_only < 0 && p <= 1) {
+                PassPlan p0 = pl[r];
+                if (p == 1) {
+                    e = plan_pass(&b->grids[r], &b->states[r], 0, b->dt[r], b->var[r], p0);
+                    if (e != GR_OK) return e;
+                }
+                e = make_pair(&b->grids[r], &b->states[r], b->dt[r], b->var[r], p0);
+                if (e == GR_OK) {
+                    if (p == 0) {
+                        pl[r] = p0;
+                        paired[r] = 1;
+                    } else {
+                        skip[r] = 1;  // pass 1 ran inside pass 0's cell launch
+                    }
+                } else if (e != GR_EUNSUPPORTED) {
+                    return e;
+                }
+            }
         }
         // ghost fill
         if (cls_mask & (1u << KC_GHOST)) {
@@ -1078,24 +1109,27 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
                 for (int met = 0; met < 2; met++)
                     for (int xg = 0; xg < 3; xg++)  // plain, dynamo, GLM
                         for (int sw = 0; sw < 2; sw++)
-                            for (int t = 0; t < (sw ? CZ_COUNT : 1); t++) {
-                                const int xi = xg == 1, gl = xg == 2;
-                                std::vector<const CellArgs *> a;
-                                std::vector<double> by;
-                                for (int r = 0; r < nr; r++) {
-                                    const Variant &V = b->var[r];
-                                    if (use[r] && V.rec == rec && V.met == met && V.xi == xi && V.glm == gl &&
-                                        (int)pl[r].swz == sw && (!sw || V.cz == t)) {
-                                        a.push_back(&pl[r].ca);
-                                        by.push_back(pl[r].ca_bytes);
+                            for (int t = 0; t < (sw ? CZ_COUNT : 1); t++)
+                                for (int pr = 0; pr < (sw ? 1 : 2); pr++) {
+                                    const int xi = xg == 1, gl = xg == 2;
+                                    std::vector<const CellArgs *> a;
+                                    std::vector<double> by;
+                                    for (int r = 0; r < nr; r++) {
+                                        const Variant &V = b->var[r];
+                                        if (use[r] && !skip[r] && V.rec == rec && V.met == met && V.xi == xi &&
+                                            V.glm == gl && (int)pl[r].swz == sw && (!sw || V.cz == t) &&
+                                            paired[r] == pr) {
+                                            a.push_back(&pl[r].ca);
+                                            by.push_back(pl[r].ca_bytes);
+                                        }
                                     }
+                                    BLaunch L;
+                                    L.cls = KC_CELL_UPDATE;
+                                    L.V = Variant{rec, met, 0, t, xi, gl};
+                                    L.swz = sw;
+                                    L.pair = pr;
+                                    add_group(stg, out, L, a, by);
                                 }
-                                BLaunch L;
-                                L.cls = KC_CELL_UPDATE;
-                                L.V = Variant{rec, met, 0, t, xi, gl};
-                                L.swz = sw;
-                                add_group(stg, out, L, a, by);
-                            }
         }
     }
     return GR_OK;
@@ -1161,9 +1195,17 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
             auto go = [&](auto X, auto GLx) {
                 constexpr bool x = decltype(X)::value != 0, gl = decltype(GLx)::value != 0;
                 if (!L.swz) {
-                    if constexpr (cell_compiled<x, gl, 1, 1>())
+                    if constexpr (cell_compiled<x, gl, 1, 1>()) {
+                        if constexpr (!gl) {
+                            if (L.pair) {
+                                hipLaunchKernelGGL((kb_cell_update<r, m, 0, 1, 1, x, false, true>), grid, dim3(kBlock),
+                                                   0, s, a, L.start, L.n);
+                                return;
+                            }
+                        }
                         hipLaunchKernelGGL((kb_cell_update<r, m, 0, 1, 1, x, gl>), grid, dim3(kBlock), 0, s, a,
                                            L.start, L.n);
+                    }
                     return;
                 }
                 with_cz(L.V.cz, [&](auto TX, auto TZ) {

@@ -1473,13 +1473,13 @@ __global__ void __launch_bounds__(kBlock) k_cell_update(CellArgs a)
 // the batched form reads its arguments through a pointer, which costs the
 // z-phase instance a few registers: it is held to the plain form's 3 waves per
 // SIMD (at the price of a few spilled registers)
-template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM>
+template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM, bool PAIR = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SWZ && !XI && !GLM ? 3 : 1)))
     kb_cell_update(const CellArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
 {
     unsigned lb;
     const CellArgs &a = aa[batch_locate<SWZ != 0>(start, n, lb)];
-    cell_body<REC, MET, SWZ, TX, TZ, XI, GLM>(a, blk_of(lb, a.gd));
+    cell_body<REC, MET, SWZ, TX, TZ, XI, GLM, PAIR>(a, blk_of(lb, a.gd));
 }
 
 }  // namespace gr
