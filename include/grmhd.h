@@ -161,7 +161,8 @@ gr_status gr_imex_stage(const gr_grid *grid, gr_state *state, int pass, double d
  * point-wise (IMEX-SSP3(4,3,3): L of stage 0 is never used and stage 1's only
  * explicit term is a_10 R_0; face-centred B, matter not frozen) they run as
  * one launch: stage 0's primitives then only seed stage 1's Newton guess and
- * its workspace block is not written (gr_imex_stage writes it). */
+ * its workspace block is not written (gr_imex_stage writes it; a batch step
+ * pairs the same passes). */
 gr_status gr_step(const gr_grid *grid, gr_state *state, double dt, hipStream_t stream);
 
 /* Primitive recovery with E and B known (Sec 2.6) on the interior cells of
