@@ -1466,7 +1466,8 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     if (status == 2) atomicAdd(io.nfail, 1ull);
 }
 template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM, bool PAIR = false>
-__global__ void __launch_bounds__(kBlock) k_cell_update(CellArgs a)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PAIR && !XI ? 3 : 1)))
+    k_cell_update(CellArgs a)
 {
     cell_body<REC, MET, SWZ, TX, TZ, XI, GLM, PAIR>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
 }
@@ -1474,7 +1475,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_update(CellArgs a)
 // z-phase instance a few registers: it is held to the plain form's 3 waves per
 // SIMD (at the price of a few spilled registers)
 template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM, bool PAIR = false>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SWZ && !XI && !GLM ? 3 : 1)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((SWZ || PAIR) && !XI && !GLM ? 3 : 1)))
     kb_cell_update(const CellArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
 {
     unsigned lb;
