@@ -13,7 +13,10 @@
 // sweeps (reconstruction + HLL, flux divergence written), one EMF launch per
 // edge direction, the CT face update, and the cell pass that runs the z sweep
 // and the sources before the accumulation.  GLM cleaning (Sec 3.1) replaces
-// the EMF and face-update launches by three more swept components.
+// the EMF and face-update launches by three more swept components.  A whole
+// step runs two consecutive point-wise passes as one cell launch where the
+// tableau allows (IMEX-SSP3: passes 0 and 1).  Device fields have rows padded
+// to whole 128-byte lines, the first interior point of a row on a line.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
