@@ -888,14 +888,13 @@ gr_status run_pass(const gr_grid *g, gr_state *st, int p, double dt, hipStream_t
 // stage 0 is never used and stage 1 has no explicit term but a_10 R_0 (its
 // faces are those of time level n): IMEX-SSP3(4,3,3).  Stage 0's primitives
 // are then kept in registers (they only seed stage 1's Newton guess).  Not
-// for GLM (stage q_B blocks), frozen matter, or when pass 1 folds stored
-// sums (the last implicit pass).
+// for GLM (stage q_B blocks), frozen matter, or two implicit stages (pass 1
+// would be the last implicit pass, which folds the stored sums).
 bool pairable(const gr_grid *g)
 {
     const Tableau T = tableau(g->imex);
     if (g->glm || g->frozen_matter || T.s < 3) return false;
-    if (needL(T, 0) || !faces_are_n(T, 1)) return false;
-    return !foldR_applies(T) || T.s - 1 != 1;
+    return !needL(T, 0) && faces_are_n(T, 1);
 }
 // p0: the plan of pass 0; adds pass 1 to its cell launch.  GR_EUNSUPPORTED
 // when the two passes are not both point-wise (they then run one by one).
