@@ -74,6 +74,7 @@ def test_validation_rejects_bad_grids():
     g2.bc[0][0] = g2.bc[0][1] = W.PERIODIC  # fewer cells than ghosts
     assert grmhd.gr_validate(g2) == grmhd.GR_EINVAL
     assert grmhd.gr_workspace_bytes(g2) == 0
+    assert grmhd.gr_field_stride(g2) == 0 and grmhd.gr_row_stride(g2) == 0 and grmhd.gr_field_origin(g2) == 0
 
 
 def test_validation_size_limits():
