@@ -30,10 +30,14 @@
  * Readings of places where the paper is silent or garbled are stated next to
  * the code that takes them.
  *
- * Parity unpinned (no closed form or printed value fixes them; they are
- * checked only through the invariants of the test-suite and agreement with
- * the HIP library): the PPM variant details (the paper names PPM only), the
- * atmosphere / failure rule, and the conductivity clamp of eq. sigma_D.
+ * Rules the paper leaves unstated are taken as readings (the PPM variant,
+ * the ghost rules, the time step convention, the atmosphere / failure
+ * fallback, the threshold and clamp of eq. sigma_D).  The test-suite pins
+ * each of them from outside this file: the rule as the reading states it,
+ * evaluated by hand (the decay rate of a cell at rest gives the eta used, the
+ * fallback state and field of forced atmosphere and failure cells, the ghost
+ * copies, the closed-form time steps), or a property every implementation of
+ * the rule has (a limited PPM parabola is monotone and keeps the cell mean).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -331,9 +335,11 @@ void or_implicit_E(double psi, double etat, double xi, const double ut[3], const
 }
 
 /* residual f_i(u~) of eq. f_u_for_e and its Jacobian J_ij (analytic, Sec 2.4).
- * Readings: in the Jacobian term "eps_ilm dE^i/du~^j B^m" the derivative is
- * of E^l; in dw~/du~^j the term "-W dE^i/du~^j" is -W dU_EM/du~^j =
- * -W E_l dE^l/du~^j; "u" in dE/du~ stands for u~. */
+ * Readings of the garbled Jacobian (Sec 2.4, eq. f_u_for_e): the Levi-Civita
+ * term of dS_EM/du~^j carries the derivative of E^l, contracted with B^m;
+ * the electric part of dw~/du~^j is W times the derivative of the field
+ * energy, -W E_l dE^l/du~^j; every velocity derivative is taken with respect
+ * to u~. */
 typedef struct {
     double gam, G1, D, tau, S[3], Es[3], B[3], et, xi;
     const metric3 *m;

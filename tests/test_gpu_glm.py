@@ -1,7 +1,7 @@
 """GLM hyperbolic divergence cleaning (Sec 3.1) in the HIP library against
 the oracle: cell-centred q_B, q_Psi and q_Phi next to the primitives after one
 and after several steps, the cell-centred divergence norms, the closed-form
-damped (B^x, Phi) oscillation and the monopole damping order of Sec 5.8, GLM
+damped (B^x, Phi) oscillation and the monopole damping order of Sec 5.1, GLM
 runs inside a batch, and the final recovery on the GLM layout."""
 import math
 import sys
@@ -121,7 +121,7 @@ def test_glm_wave_closed_form_on_gpu():
 
 
 def test_glm_monopole_damping_order_on_gpu():
-    """Sec 5.8: the divergence left at t = 0.3 falls as kappa grows"""
+    """Sec 5.1: the divergence left at t = 0.3 falls as kappa grows"""
     _torch()
     from paper_2110_03732_amd import grmhd
     out = {}

@@ -1,10 +1,10 @@
-"""GLM hyperbolic divergence cleaning in the oracle (Sec 3.1, Sec 5.8).
+"""GLM hyperbolic divergence cleaning in the oracle (Sec 3.1, Sec 5.1).
 
 Pins: the closed form of the (B^x, Phi) system of a fluid at rest,
 B'' + kappa B' + k^2 B = 0 (the GLM equations with v = 0 and Phi(0) = 0:
 a(t) = a_0 e^{-kappa t/2} [cos(w t) + kappa/(2w) sin(w t)], w^2 = k^2 -
 kappa^2/4); the paper's statement that the monopole damping grows with kappa
-(Sec 5.8: kappa = 1, 5, 10); a uniform magnetised state keeps Psi = Phi = 0
+(Sec 5.1: kappa = 1, 5, 10); a uniform magnetised state keeps Psi = Phi = 0
 and stays uniform."""
 import math
 
@@ -34,7 +34,7 @@ def test_glm_wave_closed_form(kappa):
 
 
 def test_monopole_damping_grows_with_kappa():
-    """Sec 5.8 (2-D cut of the Gaussian monopole, 64^2): at t = 0.3 the
+    """Sec 5.1 (2-D cut of the Gaussian monopole, 64^2): at t = 0.3 the
     monopole norm is ordered kappa = 1 > 5 > 10"""
     out = {}
     for kappa in (1.0, 5.0, 10.0):

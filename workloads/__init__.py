@@ -562,7 +562,7 @@ def glm_wave(n=128, k=1, kappa=1.0, b=1e-3, rho=1.0, p=1.0, recon=MC, imex=SSP2)
 
 
 def glm_monopole(n=64, kappa=1.0, R=0.2, ndim=3, ext=2.0, recon=MC, imex=SSP2):
-    """Gaussian magnetic monopole (Sec 5.8): B^x = exp(-r^2/R^2) - exp(-1) for
+    """Gaussian magnetic monopole (Sec 5.1): B^x = exp(-r^2/R^2) - exp(-1) for
     r < R, uniform rho = 1, eps = 0.1 (p = (Gamma - 1) rho eps), v = 0,
     Gamma = 5/3, eta = 1e-16, GLM with kappa_E = kappa_B = kappa, domain
     [-ext, ext]^ndim, outflow."""
