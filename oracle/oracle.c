@@ -495,7 +495,19 @@ int or_implicit(double gam, double psi, const double q[8], const double B[3], do
             if (fabs(dx[i]) > dmax) dmax = fabs(dx[i]);
             if (fabs(ut[i]) > umax) umax = fabs(ut[i]);
         }
-        if (dmax <= tol * (1.0 + umax)) {
+        /* stopping rule (reading; the paper gives none): the step is below
+         * tol [(1 + max|u~|) W^2 + (|S| + |E||B|)/w~], the size to which
+         * rounding fixes u~.  Rounding of S and tau fixes v only to a relative
+         * eps, and u~ = W v then only to eps W^2; the residual w~ u~ - (S -
+         * E x B) carries rounding of size eps (|S| + |E||B|), which a strong
+         * field makes large against w~.  A threshold without these factors
+         * cannot be met at high Lorentz factor or magnetisation; the step
+         * that meets this one is taken, and Newton's quadratic convergence
+         * leaves the iterate after it far below the threshold. */
+        double W2 = 1.0 + dotg(&m, ut, ut);
+        double Sn = sqrt(s.S[0] * s.S[0] + s.S[1] * s.S[1] + s.S[2] * s.S[2]) / (psi * psi);
+        double em = sqrt(dotg(&m, E, E) * dotg(&m, s.B, s.B));
+        if (dmax <= tol * ((1.0 + umax) * W2 + (wt > 0.0 ? (Sn + em) / wt : 0.0))) {
             /* the full Newton step is below the tolerance: take it and stop */
             for (int i = 0; i < 3; i++) ut[i] += dx[i];
             or_residual(&s, ut, f, J, E, &wt);

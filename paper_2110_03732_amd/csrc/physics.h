@@ -290,7 +290,14 @@ __device__ __forceinline__ int implicit_solve(const ImpSys &s, double tol, int m
         if (!solve3(J, mf, dx)) return 1;
         double dmax = fmax(fabs(dx[0]), fmax(fabs(dx[1]), fabs(dx[2])));
         double umax = fmax(fabs(u[0]), fmax(fabs(u[1]), fabs(u[2])));
-        if (dmax <= tol * (1.0 + umax)) {
+        // stop when the step is below tol [(1 + max|u|) W^2 + (|S| + |E||B|)/w~],
+        // the size to which rounding fixes u: S and tau fix v to a relative
+        // eps and u = W v only to eps W^2, and the residual w~ u - (S - E x B)
+        // carries rounding of size eps (|S| + |E||B|) (the step that meets
+        // the threshold is taken)
+        const double Sn = sqrt(s.S[0] * s.S[0] + s.S[1] * s.S[1] + s.S[2] * s.S[2]);
+        const double em = sqrt((e.E[0] * e.E[0] + e.E[1] * e.E[1] + e.E[2] * e.E[2]) * s.B2);
+        if (dmax <= tol * ((1.0 + umax) * (e.W * e.W) + (e.wt > 0.0 ? (Sn + em) / e.wt : 0.0))) {
             u[0] += dx[0];
             u[1] += dx[1];
             u[2] += dx[2];

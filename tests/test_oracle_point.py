@@ -159,6 +159,36 @@ def test_implicit_manufactured_root(etat):
         assert it <= 20
 
 
+@pytest.mark.parametrize("psi", [1.0, 1.3])
+@pytest.mark.parametrize("etat", [1e-8, 1e-4, 1.0, 1e4, 1e8])
+def test_implicit_manufactured_root_pin_grid(etat, psi):
+    """manufactured roots over the whole pin grid: W in {1 .. 100}, sigma in
+    {0 .. 1e4}, p/rho in {1e-6 .. 1e2}, |E| < |B|; the solve returns the state
+    within 1e-12 of the cancellation bound max(1, (tau + D)/p)"""
+    rng = np.random.default_rng(int(-math.log10(etat) * 10 + 200 + 7 * psi))
+    for W, sig, pr in itertools.product([1.0, 1.01, 2.0, 10.0, 100.0], [0.0, 1.0, 1e2, 1e4],
+                                        [1e-6, 1e-2, 1.0, 1e2]):
+        rho = 0.7
+        p = pr * rho
+        ut = math.sqrt(W * W - 1) * unit(rng) / psi ** 2
+        b = math.sqrt(sig * rho)
+        B = b * unit(rng) / psi ** 2
+        Et = 0.9 * rng.random() * b * unit(rng) / psi ** 2
+        prim = np.array([rho, *ut, p])
+        q = oracle.prim2cons(GAM, psi, prim, Et, B)
+        v = ut / W
+        Es = Et + (W / etat) * (Et + crossg(psi, v, B) - psi ** 4 * (Et @ v) * v)
+        q[5:] = psi ** 6 * Es
+        r, got, E, it = oracle.implicit(GAM, psi, q, B, etat, 0.0, prim[1:4])
+        assert r == 0, (W, sig, pr)
+        cond = max(1.0, (q[4] + q[0]) / psi ** 6 / p)
+        assert abs(got[0] - rho) / rho <= 1e-12 * cond, (W, sig, pr)
+        assert np.abs(got[1:4] - ut).max() / max(1.0, np.abs(ut).max()) <= 1e-12 * cond, (W, sig, pr)
+        assert abs(got[4] - p) / p <= 1e-12 * cond, (W, sig, pr)
+        em = max(np.abs(Et).max(), np.abs(B).max(), 1e-300)
+        assert np.abs(E - Et).max() / em <= 1e-12 * cond, (W, sig, pr)
+
+
 def test_implicit_root_is_unique_from_several_starts():
     rng = np.random.default_rng(9)
     for _ in range(30):
