@@ -8,7 +8,9 @@ IMEX-SSP3(4,3,3), FP64, seeded synthetic initial data (TOV equilibrium built
 by the generator, poloidal field from a vector potential).  A step is one
 full pass of the hot path (all IMEX stages and the final recovery).
 value = interior cells x timed steps / seconds (zone-cycles/s), inputs
-resident in HBM.  Prints one JSON line.
+resident in HBM; the step is captured once into a HIP graph and replayed, and
+the value is the median of five timed windows of K replays.  Prints one JSON
+line.
 """
 import argparse
 import json
@@ -25,6 +27,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
 
 
 def time_steps(run, dt, steps, torch):
+    """eager steps, HIP events on the run's stream; milliseconds"""
     s = run.stream
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -36,6 +39,68 @@ def time_steps(run, dt, steps, torch):
     e1.synchronize()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
+
+
+def capture_step(run, dt, grmhd, torch):
+    """one whole step (gr_step) captured into a HIP graph"""
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        grmhd.gr_step(run.grid, run.state, dt, s.cuda_stream)
+    torch.cuda.synchronize()
+    return g
+
+
+def time_replays(graph, steps, torch, windows=5):
+    """median over `windows` timed windows of `steps` graph replays (HIP
+    events on the replay stream); milliseconds per window"""
+    s = torch.cuda.Stream()
+    out = []
+    with torch.cuda.stream(s):
+        for _ in range(windows):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(steps):
+                graph.replay()
+            e1.record(s)
+            e1.synchronize()
+            out.append(e0.elapsed_time(e1))
+    torch.cuda.synchronize()
+    out.sort()
+    return out[len(out) // 2], out
+
+
+def stream_ceiling(grmhd, torch, nbytes=2 << 30, reps=5):
+    """the part's practical HBM rate: the library's hand-written streaming
+    read and copy (16-byte loads and stores) over nbytes, best of reps"""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    sink = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    s = torch.cuda.current_stream()
+    res = {}
+    for name, fn, moved in (("read", lambda: grmhd.gr_stream_read(a.data_ptr(), nbytes, sink.data_ptr(), s.cuda_stream),
+                             nbytes),
+                            ("copy", lambda: grmhd.gr_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream),
+                             2 * nbytes)):
+        fn()
+        best = None
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        res[name + "_GBps"] = round(moved / (best * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.synchronize()
+    res["bytes"] = nbytes
+    return res
 
 
 def csrc_digest():
@@ -66,12 +131,22 @@ def profiled_traffic(kernel):
     return profiled_value("*hbm_traffic.md", "traffic-bytes-per-launch", kernel)
 
 
+def profiled_step_traffic(per_kernel):
+    """counted HBM bytes per step: the per-launch traffic of every kernel
+    class times its launches per step, or None if any class is missing or
+    the sources changed since the counters were taken"""
+    tot = 0.0
+    for k, v in per_kernel.items():
+        tr = profiled_value("*hbm_traffic.md", "traffic-bytes-per-step", k)
+        if tr is None:
+            return None
+        tot += tr
+    return tot
+
+
 def profiled_fp64_flop(kernel):
     """FP64 flops per launch (rocprofv3 SQ_INSTS_VALU_*_F64)"""
     return profiled_value("*fp64_valu*.md", "fp64-flop-per-launch", kernel)
-
-
-FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
 
 
 def fp64_rate(kernel, avg_us):
@@ -103,6 +178,7 @@ def kernel_roofline(run, dt, steps, grmhd, torch):
             per[grmhd.gr_kernel_class_name(c)] = (ms, n, by)
     grmhd.gr_timing_start(0)
     name = max(per, key=lambda k: per[k][0])
+    step_bytes = sum(v[2] for v in per.values()) / steps
     ms, n, by = per[name]
     achieved = by / (ms * 1e-3) / 1e9
     return name, {
@@ -111,7 +187,7 @@ def kernel_roofline(run, dt, steps, grmhd, torch):
         "avg_launch_us": round(ms * 1e3 / n, 2), "launches": n, "alg_bytes_per_launch": by / n,
         "fp64": fp64_rate(name, ms * 1e3 / n),
     }, {k: {"ms_per_step": round(v[0] / steps, 4), "launches_per_step": v[1] / steps,
-            "alg_GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)} for k, v in per.items()}
+            "alg_GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 1)} for k, v in per.items()}, step_bytes
 
 
 def batched_vs_plain(torch, W, grmhd, nruns, steps, seed=1):
@@ -178,7 +254,7 @@ def batched_vs_plain(torch, W, grmhd, nruns, steps, seed=1):
 
 
 def served(torch, W, grmhd, nreq, rate, budgets_gib, seed=7, sweep_rates=(25.0, 50.0, 100.0, 200.0),
-           sweep_requests=48):
+           sweep_requests=48, low_rates=(2.0, 5.0, 10.0), low_requests=24):
     """Poisson stream of 2-D blast waves (64^2..512^2) and 3-D stars
     (32^3..96^3), PPM + IMEX-SSP3, 10..500 steps, eta log-uniform; the
     requests' initial data is built before the clock starts (it arrives with
@@ -210,6 +286,15 @@ def served(torch, W, grmhd, nreq, rate, budgets_gib, seed=7, sweep_rates=(25.0, 
         sweep["%g" % r] = {k: round(summ[k], 4) for k in ("offered_zone_cycles_per_s", "served_zone_cycles_per_s",
                                                           "p50_latency_s", "p99_latency_s", "makespan_s")}
     out["rate_sweep_%d_requests" % sweep_requests] = sweep
+    # below capacity: offered load under the served rate, latency without a queue
+    low = {}
+    for r in low_rates:
+        tr = W.served_trace(low_requests, rate=r, seed=seed)
+        srv = serve.Server(32 << 30, chunk=4)
+        _, summ = srv.serve(tr, payload)
+        low["%g" % r] = {k: round(summ[k], 4) for k in ("offered_zone_cycles_per_s", "served_zone_cycles_per_s",
+                                                        "p50_latency_s", "p99_latency_s", "makespan_s")}
+    out["below_capacity_%d_requests" % low_requests] = low
     # plain path, requests back to back
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -228,22 +313,47 @@ def served(torch, W, grmhd, nreq, rate, budgets_gib, seed=7, sweep_rates=(25.0, 
     return out
 
 
-def cpu_baseline(setup_fn):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(setup_fn, small_fn):
+    """the oracle as it stands on the host cores: whole IMEX-SSP3 steps of
+    the benchmark's own star until about 10 s of work (all threads), and one
+    step of the same star at 64^3 on one thread; the thread counts are the
+    ones the oracle's OpenMP runtime reports"""
     import oracle
+
+    def sample(s, min_s, max_steps):
+        st = oracle.OracleState(s)
+        dt = st.dt()
+        t0 = time.time()
+        steps = 0
+        while steps < max_steps and (steps == 0 or time.time() - t0 < min_s):
+            st.step(dt)
+            steps += 1
+        return steps, time.time() - t0
+
+    cores = oracle.threads(0)
     s = setup_fn()
-    st = oracle.OracleState(s)
-    dt = st.dt()
-    # a bounded sample: whole steps until about 10 s of work (at most 5)
-    t0 = time.time()
-    steps = 0
-    while steps < 5 and (steps == 0 or time.time() - t0 < 10.0):
-        st.step(dt)
-        steps += 1
-    el = time.time() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    steps, el = sample(s, 10.0, 5)
+    s1 = small_fn()
+    oracle.threads(1)
+    steps1, el1 = sample(s1, 0.0, 1)
+    oracle.threads(cores)
     return {"value": round(s.ncells * steps / el, 1), "unit": "zone-cycles/s", "cores": cores, "kind": "oracle",
             "sample": "%d full IMEX-SSP3 step(s) of the same %dx%dx%d star (%.1f s, OpenMP threads=%d)" % (
-                steps, s.n[0], s.n[1], s.n[2], el, cores)}
+                steps, s.n[0], s.n[1], s.n[2], el, cores),
+            "one_core": {"value": round(s1.ncells * steps1 / el1, 1), "cores": 1,
+                         "sample": "%d step of the star at %dx%dx%d on one thread (%.1f s)" % (
+                             steps1, s1.n[0], s1.n[1], s1.n[2], el1)},
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
 
 
 def main():
@@ -261,7 +371,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--copy-ref", action="store_true",
-                    help="end with a plain 256 MiB device copy, the reference kernel for scaling HBM counters")
+                    help="end with a 256 MiB streaming copy and read, the reference kernels for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one MI355X only; runs on more than one GPU are not supported "
@@ -282,12 +392,18 @@ def main():
     dt = run.dt()
     for _ in range(args.warmup):
         run.step(dt)
-    ms = time_steps(run, dt, args.steps, torch)
+    ms_eager = time_steps(run, dt, args.steps, torch)
+    graph = capture_step(run, dt, grmhd, torch)
+    graph.replay()
+    ms, windows = time_replays(graph, args.steps, torch)
     ms_per_step = ms / args.steps
     value = s.ncells * args.steps / (ms * 1e-3)
     fails = run.fail_count()
     div = run.divB()
-    extra = {"recovery_failures": int(fails), "divB_linf": float(div[2])}
+    extra = {"recovery_failures": int(fails), "divB_linf": float(div[2]),
+             "timing": "median of 5 windows of %d replays of a captured step graph" % args.steps,
+             "window_ms": [round(w, 3) for w in windows],
+             "eager_ms_per_step": round(ms_eager / args.steps, 4)}
     # elliptic cleaning of the star's face fields after the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -297,7 +413,28 @@ def main():
                            "divB_linf_before": float(before[2]), "divB_linf_after": float(after[2])}
     roof = None
     if not args.no_extra:
-        kname, roof, per_kernel = kernel_roofline(run, dt, args.steps, grmhd, torch)
+        kname, roof, per_kernel, step_bytes = kernel_roofline(run, dt, args.steps, grmhd, torch)
+        ceil = stream_ceiling(grmhd, torch)
+        # the step's algorithmic bytes: every live field read once and every
+        # output written once per IMEX pass (243 doubles per cell for
+        # IMEX-SSP3 with the metric; 218 with the two point-wise passes as one
+        # launch and the stored terms folded as the library stores them)
+        alg = 243 * 8.0 * s.ncells
+        alg218 = 218 * 8.0 * s.ncells
+        gbs = alg / (ms_per_step * 1e-3) / 1e9
+        counted = profiled_step_traffic(per_kernel)
+        roof["step"] = {
+            "alg_bytes_per_step": alg,
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "alg_bytes_per_step_218": alg218,
+            "frac_218": round(alg218 / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "launch_bytes_per_step": step_bytes,
+            "launch_bytes_note": "each launch's own inputs read once and outputs written once, summed over the "
+                                 "step's launches: includes the intermediates between kernels",
+            "counted_bytes_per_step": counted,
+            "counted_over_alg": round(counted / alg, 3) if counted else None,
+            "stream_ceiling": ceil,
+            "frac_of_copy_ceiling": round(gbs / ceil["copy_GBps"], 4)}
         # the 2-D blast wave (512^2, PPM + SSP3) as a second plain-path point
         sb = W.blast_wave(512, eta=1e-6)
         rb = grmhd.Run(sb, device="cuda:0")
@@ -315,12 +452,17 @@ def main():
             print("bench: served", file=sys.stderr, flush=True)
             extra["served"] = served(torch, W, grmhd, args.serve_requests, args.serve_rate, (32.0, 2.0))
     if args.copy_ref:
+        # reference kernels of known traffic for scaling the HBM counters:
+        # the library's streaming copy and read of 256 MiB
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
         b = torch.empty_like(a)
+        sink = torch.zeros(1, dtype=torch.float64, device="cuda:0")
         torch.cuda.synchronize()
-        b.copy_(a)
+        cs = torch.cuda.current_stream().cuda_stream
+        grmhd.gr_stream_copy(a.data_ptr(), b.data_ptr(), a.numel() * 8, cs)
+        grmhd.gr_stream_read(a.data_ptr(), a.numel() * 8, sink.data_ptr(), cs)
         torch.cuda.synchronize()
-        extra["copy_ref_bytes"] = 2 * a.numel() * 8
+        extra["copy_ref_bytes"] = {"k_stream_copy": 2 * a.numel() * 8, "k_stream_read": a.numel() * 8}
     out = {
         "metric": "zone-cycles/s per IMEX-RK step FP64 (plain single grid)",
         "value": round(value, 1),
@@ -341,7 +483,7 @@ def main():
         "extra": extra,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(star)
+        out["cpu_baseline"] = cpu_baseline(star, lambda: W.tov_star(64))
     print(json.dumps(out), flush=True)
 
 

@@ -239,14 +239,32 @@ typedef struct gr_batch gr_batch;
  * keeps the default tiles; "" times the tile candidates of every class of
  * runs (recon, metric, ndim) on these runs and keeps the fastest; a path
  * does the same for the classes not yet listed in that text file and
- * appends its decisions to it.  Allocates the argument block (hipMalloc) and
- * synchronises the stream.  GR_EUNSUPPORTED if the runs mix IMEX tableaux. */
+ * appends its decisions to it.  Allocates the argument block (hipMalloc,
+ * with spare room for later updates) and its pinned host staging
+ * (hipHostMalloc), and synchronises the stream.  GR_EUNSUPPORTED if the runs
+ * mix IMEX tableaux. */
 gr_status gr_batch_create(gr_batch **batch, const gr_grid *grids, const gr_state *states, const double *dt,
                           int nruns, const char *tune_cache, hipStream_t stream);
 
-/* Replace the time steps (host array of nruns); synchronises the stream and
- * rebuilds the argument block (a later gr_batch_run captures a new graph). */
+/* Replace the time steps (host array of nruns) and rewrite the argument
+ * block, ordered on the stream after the work already queued there (a later
+ * gr_batch_run captures a new graph). */
 gr_status gr_batch_set_dt(gr_batch *batch, const double *dt, hipStream_t stream);
+
+/* Replace the batch's runs by nruns others (a continuous-batching loop
+ * admits and retires runs this way; not in the paper, which has no many-run
+ * mode).  Same conventions as gr_batch_create, with the batch's IMEX
+ * tableau (GR_EUNSUPPORTED otherwise); runs of a class the batch already
+ * holds keep that class's tiles, others get the default ones.  The launch
+ * list is re-planned on the host and the argument block is rewritten in the
+ * batch's device block, ordered on the stream after the work already queued
+ * there, without a host synchronisation; the device block is reallocated
+ * (after synchronising the stream) only when the new list does not fit its
+ * spare room.  Launch the batch on the same stream afterwards (or order the
+ * other stream after it).  A captured graph is dropped.  On error the batch
+ * holds no launches until the next successful update. */
+gr_status gr_batch_update(gr_batch *batch, const gr_grid *grids, const gr_state *states, const double *dt,
+                          int nruns, hipStream_t stream);
 
 /* One step of every run, launched eagerly on the stream. */
 gr_status gr_batch_step(gr_batch *batch, hipStream_t stream);
@@ -267,9 +285,19 @@ gr_status gr_batch_stats(const gr_batch *batch, int *launches_per_step, double *
 gr_status gr_batch_tiles(const gr_batch *batch, int run, int *xy_tile, int *cz_tile);
 const char *gr_tile_name(int which, int tile);
 
-/* Free the batch (argument block and graph).  Does not synchronise: the
+/* Free the batch (argument block, staging buffers and graph).  Waits for
+ * the batch's own argument copies; otherwise does not synchronise: the
  * caller makes sure no launch of the batch is still pending. */
 gr_status gr_batch_destroy(gr_batch *batch);
+
+/* Measurement hooks (not part of the method): a streaming read of `bytes`
+ * bytes at src, and a streaming copy of `bytes` bytes from src to dst, with
+ * 16-byte loads and stores (device pointers, 16-byte aligned, bytes a
+ * multiple of 16, GR_EINVAL otherwise).  sink is one device double that the
+ * read never writes for finite data.  Their bandwidth is the practical HBM
+ * ceiling the stencil kernels are measured against; asynchronous. */
+gr_status gr_stream_read(const void *src, size_t bytes, double *sink, hipStream_t stream);
+gr_status gr_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

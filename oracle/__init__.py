@@ -79,6 +79,8 @@ def lib():
         L.or_step_glm.restype = ctypes.c_long
         L.or_explicit_L_glm.argtypes = [G, _DD, _D, _D, _DD]
         L.or_divB_glm.argtypes = [G, _DD, _D]
+        L.or_threads.argtypes = [ctypes.c_int]
+        L.or_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -307,6 +309,11 @@ def tableau(imex):
     w = np.zeros(4)
     s = lib().or_tableau(imex, _p(At), _p(A), _p(wt), _p(w))
     return At.reshape(4, 4)[:s, :s], A.reshape(4, 4)[:s, :s], wt[:s], w[:s]
+
+
+def threads(n=0):
+    """OpenMP threads of the oracle: n > 0 sets them; returns the count in use"""
+    return lib().or_threads(int(n))
 
 
 def run(s, steps=None, dt=None):

@@ -42,6 +42,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------- */
 /* problem description (mirrored by a ctypes Structure in oracle/__init__.py) */
@@ -1903,4 +1906,17 @@ void or_divB_glm(const or_grid *G, double **qB, double out[3])
     out[0] = s1 / cnt;
     out[1] = sqrt(s2 / cnt);
     out[2] = mx;
+}
+
+/* OpenMP threads of the per-face / per-edge loops: n > 0 sets them; returns
+ * the count in use (the CPU-baseline timing states it) */
+int or_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

@@ -124,8 +124,17 @@ __device__ __forceinline__ double frcp(double x)
 // ---------------------------------------------------------------------------
 // reconstruction (Sec 5: minmod, MC, PPM).  Per-cell form: the left and right
 // interface values (aL, aR) of cell 0 from its neighbours a[-2..2].
+//
+// Rounding policy: the limiters and their switch predicates are evaluated
+// without contraction (no fused multiply-add), each product and sum rounded
+// as written, in the expression order of the plain definition; the one
+// deliberate difference is the CW threshold d^2/6, formed as d^2 * (1/6).
+// Every switch of these limiters is continuous at its threshold (the value
+// on either side agrees there), so a decision that a rounding difference
+// moves changes the result by an amount of the order of that difference.
 __device__ __forceinline__ double minmod2(double a, double b)
 {
+#pragma clang fp contract(off)
     if (a * b <= 0.0) return 0.0;
     return fabs(a) < fabs(b) ? a : b;
 }
@@ -138,6 +147,7 @@ __device__ __forceinline__ double minmod3(double a, double b, double c)
 // Colella-Woodward fourth-order interface value, clipped between neighbours
 __device__ __forceinline__ double ppm_iface(double am1, double a0, double a1, double a2)
 {
+#pragma clang fp contract(off)
     double v = 7.0 / 12.0 * (a0 + a1) - 1.0 / 12.0 * (am1 + a2);
     double lo = fmin(a0, a1), hi = fmax(a0, a1);
     return fmin(fmax(v, lo), hi);
@@ -145,6 +155,7 @@ __device__ __forceinline__ double ppm_iface(double am1, double a0, double a1, do
 // the two CW monotonicity constraints (no steepening, no flattening)
 __device__ __forceinline__ void ppm_mono(double a, double &aL, double &aR)
 {
+#pragma clang fp contract(off)
     if ((aR - a) * (a - aL) <= 0.0) {
         aL = a;
         aR = a;
@@ -162,6 +173,7 @@ template <int REC>
 __device__ __forceinline__ void recon_cell(double am2, double am1, double a0, double ap1, double ap2, double &aL,
                                           double &aR)
 {
+#pragma clang fp contract(off)
     if (REC == GR_MINMOD) {
         double s = minmod2(a0 - am1, ap1 - a0);
         aL = a0 - 0.5 * s;

@@ -958,7 +958,13 @@ struct gr_batch {
     int s = 0;
     std::vector<BLaunch> launches;
     void *dev = nullptr;
-    size_t dev_bytes = 0;
+    size_t dev_bytes = 0, dev_cap = 0;
+    // pinned host staging of the argument block, two buffers used in turn;
+    // each event marks the end of the last copy out of its buffer
+    void *host[2] = {nullptr, nullptr};
+    size_t host_cap[2] = {0, 0};
+    hipEvent_t host_ev[2] = {nullptr, nullptr};
+    int host_next = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
@@ -1156,6 +1162,50 @@ gr_status upload(Staging &stg, std::vector<BLaunch> &ls, void **dev, size_t *byt
     return GR_OK;
 }
 
+// write the argument block of the batch's launch list into its device
+// block, stream-ordered on s: from a pinned staging buffer (the one not used
+// by the previous upload, whose copy must have finished before it is reused),
+// without a host synchronisation.  The device block grows, with spare room,
+// only when the list no longer fits; the old one is freed after the work
+// queued on s that may read it.
+gr_status upload_batch(gr_batch *b, const Staging &stg, hipStream_t s)
+{
+    const size_t n = stg.buf.size();
+    b->dev_bytes = n;
+    if (n == 0) return GR_OK;
+    if (n > b->dev_cap) {
+        if (b->dev) {
+            HIPCHK(hipStreamSynchronize(s));
+            (void)hipFree(b->dev);
+            b->dev = nullptr;
+            b->dev_cap = 0;
+        }
+        const size_t cap = n + n / 2 + 4096;
+        HIPCHK(hipMalloc(&b->dev, cap));
+        b->dev_cap = cap;
+    }
+    const int h = b->host_next;
+    b->host_next ^= 1;
+    if (b->host_ev[h]) HIPCHK(hipEventSynchronize(b->host_ev[h]));
+    else HIPCHK(hipEventCreateWithFlags(&b->host_ev[h], hipEventDisableTiming));
+    if (n > b->host_cap[h]) {
+        if (b->host[h]) (void)hipHostFree(b->host[h]);
+        b->host[h] = nullptr;
+        b->host_cap[h] = 0;
+        const size_t cap = n + n / 2 + 4096;
+        HIPCHK(hipHostMalloc(&b->host[h], cap, hipHostMallocDefault));
+        b->host_cap[h] = cap;
+    }
+    std::memcpy(b->host[h], stg.buf.data(), n);
+    HIPCHK(hipMemcpyAsync(b->dev, b->host[h], n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(b->host_ev[h], s));
+    for (auto &L : b->launches) {
+        L.args = (const char *)b->dev + L.args_off;
+        L.start = (const unsigned *)((const char *)b->dev + L.start_off);
+    }
+    return GR_OK;
+}
+
 gr_status launch_b(const BLaunch &L, hipStream_t s)
 {
     if (L.total == 0) return GR_OK;
@@ -1248,18 +1298,32 @@ void drop_graph(gr_batch *b)
 gr_status rebuild(gr_batch *b, hipStream_t s)
 {
     drop_graph(b);
-    if (b->dev) (void)hipFree(b->dev);
-    b->dev = nullptr;
     b->launches.clear();
+    b->bytes_step = 0.0;
     Staging stg;
     std::vector<char> all(b->grids.size(), 1);
-    gr_status e = build_launches(b, -1, ~0u, all, stg, b->launches);
+    std::vector<BLaunch> ls;
+    gr_status e = build_launches(b, -1, ~0u, all, stg, ls);
     if (e != GR_OK) return e;
-    e = upload(stg, b->launches, &b->dev, &b->dev_bytes, s);
-    if (e != GR_OK) return e;
-    b->bytes_step = 0.0;
+    b->launches.swap(ls);
+    e = upload_batch(b, stg, s);
+    if (e != GR_OK) {
+        b->launches.clear();
+        return e;
+    }
     for (const auto &L : b->launches) b->bytes_step += L.bytes;
     return GR_OK;
+}
+
+// the runs' interior cells
+long batch_cells(const gr_batch *b)
+{
+    long c = 0;
+    for (const auto &g : b->grids) {
+        Geo G = make_geo(&g);
+        c += (long)G.n[0] * G.n[1] * G.n[2];
+    }
+    return c;
 }
 
 // ---- autotuner.  Runs are classed by (recon, metric, dimensionality); for
@@ -1393,10 +1457,71 @@ gr_status tune(gr_batch *b, const char *cache, hipStream_t s)
     return status;
 }
 
+// ---------------------------------------------------------------------------
+// measurement hooks: a streaming read and a streaming copy with 16-byte
+// loads and stores, four per thread issued before any is used; the practical
+// HBM ceiling that the stencil kernels are compared with
+constexpr int kStreamPer = 4;
+__global__ void __launch_bounds__(kBlock) k_stream_read(const double2 *__restrict__ src, size_t n2, double *sink)
+{
+    const size_t base = (size_t)blockIdx.x * (kBlock * kStreamPer) + threadIdx.x;
+    double2 v[kStreamPer];
+#pragma unroll
+    for (int k = 0; k < kStreamPer; k++) {
+        const size_t i = base + (size_t)k * kBlock;
+        v[k] = i < n2 ? src[i] : make_double2(0.0, 0.0);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kStreamPer; k++) acc += v[k].x + v[k].y;
+    if (acc == -1.0e308) sink[0] = acc;  // never for the finite data read here: keeps the loads live
+}
+__global__ void __launch_bounds__(kBlock) k_stream_copy(const double2 *__restrict__ src, double2 *__restrict__ dst,
+                                                        size_t n2)
+{
+    const size_t base = (size_t)blockIdx.x * (kBlock * kStreamPer) + threadIdx.x;
+    double2 v[kStreamPer];
+#pragma unroll
+    for (int k = 0; k < kStreamPer; k++) {
+        const size_t i = base + (size_t)k * kBlock;
+        if (i < n2) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kStreamPer; k++) {
+        const size_t i = base + (size_t)k * kBlock;
+        if (i < n2) dst[i] = v[k];
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
 extern "C" {
+
+gr_status gr_stream_read(const void *src, size_t bytes, double *sink, hipStream_t s)
+{
+    if (!src || !sink || bytes % 16 || ((uintptr_t)src & 15)) return GR_EINVAL;
+    const size_t n2 = bytes / 16;
+    if (n2 == 0) return GR_OK;
+    const size_t nb = (n2 + kBlock * kStreamPer - 1) / (kBlock * kStreamPer);
+    if (nb > 0x7fffffffu) return GR_EINVAL;
+    hipLaunchKernelGGL(k_stream_read, dim3((unsigned)nb), dim3(kBlock), 0, s, (const double2 *)src, n2, sink);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+gr_status gr_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    if (!src || !dst || bytes % 16 || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return GR_EINVAL;
+    const size_t n2 = bytes / 16;
+    if (n2 == 0) return GR_OK;
+    const size_t nb = (n2 + kBlock * kStreamPer - 1) / (kBlock * kStreamPer);
+    if (nb > 0x7fffffffu) return GR_EINVAL;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)nb), dim3(kBlock), 0, s, (const double2 *)src, (double2 *)dst,
+                       n2);
+    LAUNCHCHK();
+    return GR_OK;
+}
 
 int gr_abi_version(void) { return GR_ABI_VERSION; }
 
@@ -1846,15 +1971,12 @@ gr_status gr_batch_create(gr_batch **out, const gr_grid *grids, const gr_state *
     b->states.assign(states, states + nruns);
     b->dt.assign(dt, dt + nruns);
     b->s = tableau(grids[0].imex).s;
-    b->cells = 0;
-    for (int r = 0; r < nruns; r++) {
-        b->var.push_back(default_variant(&grids[r]));
-        Geo G = make_geo(&grids[r]);
-        b->cells += (long)G.n[0] * G.n[1] * G.n[2];
-    }
+    for (int r = 0; r < nruns; r++) b->var.push_back(default_variant(&grids[r]));
+    b->cells = batch_cells(b);
     gr_status e = GR_OK;
     if (tune_cache) e = tune(b, tune_cache, s);
     if (e == GR_OK) e = rebuild(b, s);
+    if (e == GR_OK && hipStreamSynchronize(s) != hipSuccess) e = GR_EHIP;
     if (e != GR_OK) {
         gr_batch_destroy(b);
         return e;
@@ -1868,8 +1990,42 @@ gr_status gr_batch_set_dt(gr_batch *b, const double *dt, hipStream_t s)
     if (!b || !dt) return GR_EINVAL;
     for (size_t r = 0; r < b->dt.size(); r++)
         if (!(dt[r] > 0.0)) return GR_EINVAL;
-    HIPCHK(hipStreamSynchronize(s));  // the old argument block may still be in use
     b->dt.assign(dt, dt + b->dt.size());
+    return rebuild(b, s);  // the block is rewritten after the work already queued on s
+}
+
+gr_status gr_batch_update(gr_batch *b, const gr_grid *grids, const gr_state *states, const double *dt, int nruns,
+                          hipStream_t s)
+{
+    if (!b || !grids || !states || !dt || nruns < 1 || b->grids.empty()) return GR_EINVAL;
+    for (int r = 0; r < nruns; r++) {
+        gr_status v = gr_validate(&grids[r]);
+        if (v != GR_OK) return v;
+        v = check_state(&grids[r], &states[r]);
+        if (v != GR_OK) return v;
+        if (!(dt[r] > 0.0)) return GR_EINVAL;
+        if (grids[r].imex != b->grids[0].imex) return GR_EUNSUPPORTED;
+    }
+    // runs of a class the batch already holds keep that class's tiles
+    std::vector<Variant> var;
+    for (int r = 0; r < nruns; r++) {
+        const gr_grid &g = grids[r];
+        Variant V = default_variant(&g);
+        for (size_t o = 0; o < b->grids.size() && !g.glm; o++) {
+            const gr_grid &h = b->grids[o];
+            if (!h.glm && h.recon == g.recon && (h.metric ? 1 : 0) == (g.metric ? 1 : 0) && h.ndim == g.ndim) {
+                V.xy = b->var[o].xy;
+                V.cz = b->var[o].cz;
+                break;
+            }
+        }
+        var.push_back(V);
+    }
+    b->grids.assign(grids, grids + nruns);
+    b->states.assign(states, states + nruns);
+    b->dt.assign(dt, dt + nruns);
+    b->var.swap(var);
+    b->cells = batch_cells(b);
     return rebuild(b, s);
 }
 
@@ -1934,6 +2090,13 @@ gr_status gr_batch_destroy(gr_batch *b)
     if (!b) return GR_OK;
     drop_graph(b);
     if (b->dev) (void)hipFree(b->dev);
+    for (int h = 0; h < 2; h++) {
+        if (b->host_ev[h]) {
+            (void)hipEventSynchronize(b->host_ev[h]);
+            (void)hipEventDestroy(b->host_ev[h]);
+        }
+        if (b->host[h]) (void)hipHostFree(b->host[h]);
+    }
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
     return GR_OK;

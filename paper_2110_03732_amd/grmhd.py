@@ -19,8 +19,8 @@ EXPORTED = ["gr_abi_version", "gr_strerror", "gr_validate", "gr_field_stride", "
             "gr_workspace_bytes",
             "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim", "gr_divB_norm",
             "gr_cfl_dt", "gr_fail_count", "gr_timing_start", "gr_timing_read", "gr_kernel_class_name",
-            "gr_clean_divB", "gr_batch_create", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run", "gr_batch_stats", "gr_batch_tiles",
-            "gr_tile_name", "gr_batch_destroy"]
+            "gr_clean_divB", "gr_batch_create", "gr_batch_update", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run",
+            "gr_batch_stats", "gr_batch_tiles", "gr_tile_name", "gr_batch_destroy", "gr_stream_read", "gr_stream_copy"]
 
 
 class GrError(RuntimeError):
@@ -85,6 +85,7 @@ def lib():
         L.gr_kernel_class_name.restype = ctypes.c_char_p
         PB = ctypes.POINTER(ctypes.c_void_p)
         L.gr_batch_create.argtypes = [PB, G, S, D, ctypes.c_int, ctypes.c_char_p, V]
+        L.gr_batch_update.argtypes = [V, G, S, D, ctypes.c_int, V]
         L.gr_batch_set_dt.argtypes = [V, D, V]
         L.gr_batch_step.argtypes = [V, V]
         L.gr_batch_run.argtypes = [V, ctypes.c_int, V]
@@ -93,8 +94,10 @@ def lib():
         L.gr_tile_name.argtypes = [ctypes.c_int, ctypes.c_int]
         L.gr_tile_name.restype = ctypes.c_char_p
         L.gr_batch_destroy.argtypes = [V]
-        for name in ("gr_batch_create", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run", "gr_batch_stats",
-                     "gr_batch_tiles", "gr_batch_destroy"):
+        L.gr_stream_read.argtypes = [V, ctypes.c_size_t, V, V]
+        L.gr_stream_copy.argtypes = [V, V, ctypes.c_size_t, V]
+        for name in ("gr_batch_create", "gr_batch_update", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run",
+                     "gr_batch_stats", "gr_batch_tiles", "gr_batch_destroy", "gr_stream_read", "gr_stream_copy"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("gr_timing_start", "gr_timing_read", "gr_validate", "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim",
                      "gr_divB_norm", "gr_cfl_dt", "gr_fail_count"):
@@ -211,6 +214,22 @@ def gr_batch_create(grids, states, dt, tune_cache, stream):
     tc = None if tune_cache is None else tune_cache.encode()
     _chk(lib().gr_batch_create(ctypes.byref(h), ga, sa, da, n, tc, stream))
     return h
+
+
+def gr_batch_update(batch, grids, states, dt, stream):
+    n = len(grids)
+    ga = (gr_grid * n)(*grids)
+    sa = (gr_state * n)(*states)
+    da = (ctypes.c_double * n)(*[float(x) for x in dt])
+    _chk(lib().gr_batch_update(batch, ga, sa, da, n, stream))
+
+
+def gr_stream_read(src_dev_ptr, nbytes, sink_dev_ptr, stream):
+    _chk(lib().gr_stream_read(src_dev_ptr, nbytes, sink_dev_ptr, stream))
+
+
+def gr_stream_copy(src_dev_ptr, dst_dev_ptr, nbytes, stream):
+    _chk(lib().gr_stream_copy(src_dev_ptr, dst_dev_ptr, nbytes, stream))
 
 
 def gr_batch_set_dt(batch, dt, stream):
@@ -379,11 +398,6 @@ class Run:
     def faces(self):
         return self._block(self.face, 3)
 
-    def E(self):
-        q = self.cons()
-        ps6 = 1.0 if not self.setup.metric else self.setup.psi ** 6
-        return q[5:8] / ps6
-
     def work_field(self, kind, stage, field):
         off = gr_workspace_offset(self.grid, kind, stage, field) // 8
         self.stream.synchronize()
@@ -402,6 +416,16 @@ class Batch:
         self.stream = stream if stream is not None else runs[0].stream
         self.h = gr_batch_create([r.grid for r in self.runs], [r.state for r in self.runs], self.dts, tune_cache,
                                  self.stream.cuda_stream)
+
+    def update(self, runs, dts):
+        """replace the batch's runs (stream-ordered, no host synchronisation);
+        the runs' state must stay alive while the batch may still use it"""
+        if not runs:
+            raise ValueError("empty batch")
+        self.runs = list(runs)
+        self.dts = [float(x) for x in dts]
+        gr_batch_update(self.h, [r.grid for r in self.runs], [r.state for r in self.runs], self.dts,
+                        self.stream.cuda_stream)
 
     def step(self):
         gr_batch_step(self.h, self.stream.cuda_stream)

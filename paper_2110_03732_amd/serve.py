@@ -3,17 +3,21 @@
 Requests (one solve each: initial data, time step count) arrive over time.
 The loop admits queued requests in arrival order while their device memory
 fits the HBM budget, keeps every admitted run's state resident on the
-device, and advances all resident runs together: each iteration launches a
-chunk of steps of one batch (gr_batch_*) on a compute stream, then -- while
-the device works -- admits and initialises newly arrived requests on the
-default stream; finished runs leave and free their memory, and the next
-chunk runs with the new membership.  A run's result does not depend on the
-other runs in the batch (the kernels compute every cell of a run with the
-same arithmetic), so the result of a request is the same alone and in the
-mix.
+device, and advances all resident runs together: each iteration launches up
+to a chunk of steps of one batch (gr_batch_*) on a compute stream, then --
+while the device works -- admits and initialises newly arrived requests on
+the default stream.  A run leaves the batch right after its own last step
+(gr_batch_update rewrites the batch's argument block in place, ordered on
+the compute stream, with no host synchronisation), so a short request never
+shortens the chunk of the others; newly admitted runs join at the next
+iteration.  A run's result does not depend on the other runs in the batch
+(the kernels compute every cell of a run with the same arithmetic), so the
+result of a request is the same alone and in the mix.
 
-Latency of a request = completion time - arrival time, on the host clock
-that also releases the arrivals.
+Latency of a request = completion time - arrival time on the host clock
+that also releases the arrivals; the completion time is that of the request's
+last step on the device (an event after it, placed on the host clock through
+an event recorded and waited for at the start).
 """
 from __future__ import annotations
 
@@ -42,8 +46,10 @@ class _Slot:
 
 class Server:
     """hbm_budget: bytes of device memory the resident runs may hold.
-    chunk: steps per iteration (fewer when a run finishes earlier).
-    keep: copy each finished run's primitives to the host (for checks)."""
+    chunk: steps per iteration (a run that finishes inside it leaves the
+    batch after its own last step).
+    keep: copy each finished run's primitives, faces and conserved
+    variables to the host (for checks)."""
 
     def __init__(self, hbm_budget, device="cuda:0", chunk=4, tune_cache=None, keep=False, max_runs=1024):
         import torch
@@ -67,11 +73,16 @@ class Server:
         active = []
         used = 0
         batch = None
-        dirty = True
+        dirty = False
         records = []
         peak = 0
         iters = 0
+        updates = 0
         t0 = clock()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev0.record(self.compute)
+        ev0.synchronize()
+        t_ev0 = clock() - t0
 
         def admit(now):
             nonlocal used, dirty, peak
@@ -88,55 +99,77 @@ class Server:
                 queue.popleft()
                 run = grmhd.Run(setup, device=self.device, stream=self.init_stream)
                 dt = run.dt()
-                active.append(_Slot(req, run, dt, int(req["steps"]), nb, clock() - t0))
+                slot = _Slot(req, run, dt, int(req["steps"]), nb, clock() - t0)
                 used += nb
                 peak = max(peak, used)
+                if slot.left == 0:
+                    finish(slot, clock() - t0)
+                    used -= nb
+                    continue
+                active.append(slot)
                 dirty = True
 
+        def finish(s, t_done):
+            rec = dict(rid=s.req["rid"], arrival=s.req["arrival"], admit=s.admit, done=t_done,
+                       latency=t_done - s.req["arrival"], steps=int(s.req["steps"]),
+                       cells=int(s.run.setup.ncells), fails=None)
+            if self.keep:
+                rec["prims"] = s.run.prims()
+                rec["faces"] = s.run.faces()
+                rec["cons"] = s.run.cons()
+                rec["fails"] = s.run.fail_count()
+            records.append(rec)
+
+        def set_members(slots):
+            nonlocal batch, updates
+            runs, dts = [s.run for s in slots], [s.dt for s in slots]
+            if batch is None:
+                self.compute.wait_stream(self.init_stream)  # new runs are initialised on the default stream
+                batch = grmhd.Batch(runs, dts, tune_cache=self.tune_cache, stream=self.compute)
+            else:
+                batch.update(runs, dts)
+                updates += 1
+
         while pending or queue or active:
-            now = clock() - t0
-            admit(now)
+            admit(clock() - t0)
             if not active:
                 if pending:
                     time.sleep(max(0.0, min(pending[0]["arrival"] - (clock() - t0), 0.01)))
                 continue
             if dirty:
-                if batch is not None:
-                    batch.close()
-                self.compute.wait_stream(self.init_stream)  # new runs are initialised on the default stream
-                batch = grmhd.Batch([s.run for s in active], [s.dt for s in active], tune_cache=self.tune_cache,
-                                    stream=self.compute)
+                self.compute.wait_stream(self.init_stream)
+                set_members(active)
                 dirty = False
-            stepping = list(active)  # the batch's members; admissions below join the next batch
-            k = min(self.chunk, min(s.left for s in stepping))
-            for _ in range(k):
+            stepping = list(active)
+            finished = []
+            for _ in range(min(self.chunk, max(s.left for s in stepping))):
                 batch.step()
-            done_ev = torch.cuda.Event()
-            done_ev.record(self.compute)
+                for s in stepping:
+                    s.left -= 1
+                    s.run.t += s.dt
+                done_now = [s for s in stepping if s.left == 0]
+                if done_now:
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(self.compute)
+                    finished += [(s, ev) for s in done_now]
+                    stepping = [s for s in stepping if s.left > 0]
+                    if not stepping:
+                        break
+                    set_members(stepping)
+            end_ev = torch.cuda.Event()
+            end_ev.record(self.compute)
             iters += 1
             # host work overlapping the chunk: arrivals and admissions
             admit(clock() - t0)
-            done_ev.synchronize()
-            t_done = clock() - t0
-            stepped = set(id(s) for s in stepping)
-            keep_slots = [s for s in active if id(s) not in stepped]
-            for s in stepping:
-                s.left -= k
-                s.run.t += k * s.dt
-                if s.left > 0:
-                    keep_slots.append(s)
-                    continue
-                rec = dict(rid=s.req["rid"], arrival=s.req["arrival"], admit=s.admit, done=t_done,
-                           latency=t_done - s.req["arrival"], steps=int(s.req["steps"]),
-                           cells=int(s.run.setup.ncells), fails=None)
-                if self.keep:
-                    rec["prims"] = s.run.prims()
-                    rec["faces"] = s.run.faces()
-                    rec["fails"] = s.run.fail_count()
-                records.append(rec)
+            end_ev.synchronize()
+            gone = set()
+            for s, ev in finished:
+                finish(s, t_ev0 + ev0.elapsed_time(ev) * 1e-3)
                 used -= s.bytes
-                dirty = True
-            active = keep_slots
+                gone.add(id(s))
+            active = [s for s in active if id(s) not in gone]
+            # the batch now holds `stepping`; runs admitted during the chunk
+            # (dirty) join at the next iteration
         if batch is not None:
             batch.close()
         makespan = clock() - t0
@@ -149,5 +182,6 @@ class Server:
                        offered_zone_cycles_per_s=zc / span if span > 0 else None,
                        p50_latency_s=float(np.percentile(lat, 50)) if len(lat) else None,
                        p99_latency_s=float(np.percentile(lat, 99)) if len(lat) else None,
-                       iterations=iters, peak_resident_bytes=peak, hbm_budget_bytes=self.budget)
+                       iterations=iters, batch_updates=updates, peak_resident_bytes=peak,
+                       hbm_budget_bytes=self.budget)
         return records, summary

@@ -3,13 +3,17 @@ alone and in the mix, under an HBM budget small enough that requests queue,
 join and leave the batch at different times.  Alone = the request served by
 itself (the same batched kernels: exact) and the request stepped through the
 single-grid path (separately compiled kernels: within 1e-13 of each field's
-scale)."""
+scale).  Every served result is also compared with the CPU oracle run for
+the same steps (relative L1 <= 1e-10 and element-wise <= 1e-9 of each
+field's scale, as the one-step parity tests; the requests take 2-9 steps)."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import workloads as W
+from parity import state_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +57,17 @@ def test_served_equals_alone():
                 assert np.abs(got[f] - want[f]).max() <= 1e-13 * max(np.abs(want[f]).max(), 1e-300), rec["rid"]
         assert run.fail_count() == rec["fails"]
         assert rec["latency"] > 0.0 and rec["done"] >= rec["admit"] >= rec["arrival"] - 1e-9
+        # the served result against the oracle
+        ref = oracle.OracleState(s)
+        for _ in range(req["steps"]):
+            ref.step(dt)
+        ps6 = 1.0 if not s.metric else s.psi ** 6
+        Eg = rec["cons"][5:8] / ps6
+        Er = np.stack([ref.q[5 + i] / ps6 for i in range(3)])
+        errs = state_errors(s, rec["prims"], ref.prim, Eg, Er, rec["faces"], ref.face)
+        bad = [e for e in errs if not (e[1] <= 1e-10 and e[2] <= 1e-9)]
+        assert not bad, (rec["rid"], bad)
+        assert rec["fails"] == ref.nfail
 
 
 def test_serve_edge_cases():

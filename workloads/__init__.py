@@ -524,6 +524,68 @@ def random_states(shape3, seed=1, wmax=10.0, sigma_max=10.0, emax_frac=0.5, rho_
     return s
 
 
+def pin_grid_states(seed=1, metric=None, reps=2, efrac=0.9):
+    """Point-wise cases over the grid of the oracle's own pins: W in {1, 1.01,
+    2, 10, 100}, magnetisation sigma = B^2/rho in {0, 1, 1e2, 1e4}, p/rho in
+    {1e-6, 1e-2, 1, 1e2}, each combination `reps` times with seeded
+    directions of u~, B and E (|E| = efrac |B| times a seeded factor in
+    [0, 1)); rho = 0.7.  A 1-D row of cells (B^y, B^z cell values; the x-face
+    values chosen so that the mean of a cell's two faces is its B^x).
+    metric = (alpha, psi): a constant lapse and conformal factor (components
+    scaled by psi^-2 so that W and sigma hold in the orthonormal frame)."""
+    Ws = [1.0, 1.01, 2.0, 10.0, 100.0]
+    sigs = [0.0, 1.0, 1e2, 1e4]
+    prs = [1e-6, 1e-2, 1.0, 1e2]
+    combos = [(w, sg, pr) for w in Ws for sg in sigs for pr in prs] * reps
+    n = len(combos)
+    s = _blank(Setup("pin_grid", 1, (n, 1, 1), 2, (0, 0, 0), (1, 1, 1), _bc(1, OUTFLOW), 5.0 / 3.0, MINMOD, SSP2,
+                     eta=1e-3, rho_atm=1e-12, p_atm=1e-20))
+    g = s.ng
+    dirs = [uniform_pm1(seed, 20 + k, 3 * n).reshape(n, 3) for k in range(3)]
+    fac = 0.5 * (uniform_pm1(seed, 23, n) + 1.0)
+    ps2 = 1.0 if metric is None else metric[1] ** 2
+    rho = 0.7
+    bc = np.zeros((n, 3))
+    for c, (w, sg, pr) in enumerate(combos):
+        i = g + c
+        du = dirs[0][c] / (np.linalg.norm(dirs[0][c]) + 1e-300)
+        db = dirs[1][c] / (np.linalg.norm(dirs[1][c]) + 1e-300)
+        de = dirs[2][c] / (np.linalg.norm(dirs[2][c]) + 1e-300)
+        s.prim[0][0, 0, i] = rho
+        s.prim[4][0, 0, i] = pr * rho
+        um = math.sqrt(w * w - 1.0)
+        for d in range(3):
+            s.prim[1 + d][0, 0, i] = um * du[d] / ps2
+        b = math.sqrt(sg * rho)
+        bc[c] = b * db / ps2
+        for d in range(3):
+            s.E[d][0, 0, i] = efrac * fac[c] * b * de[d] / ps2
+    # ghosts: copies of the first / last cell
+    for v in range(5):
+        s.prim[v][0, 0, :g] = s.prim[v][0, 0, g]
+        s.prim[v][0, 0, g + n:] = s.prim[v][0, 0, g + n - 1]
+    for d in range(3):
+        s.E[d][0, 0, :g] = s.E[d][0, 0, g]
+        s.E[d][0, 0, g + n:] = s.E[d][0, 0, g + n - 1]
+    pf = 1.0 if metric is None else metric[1] ** 6
+    face = np.zeros((3,) + s.shape)
+    fx = np.zeros(s.shape[2])
+    fx[:g + 1] = bc[0, 0] * pf
+    for c in range(n):
+        fx[g + c + 1] = 2.0 * bc[c, 0] * pf - fx[g + c]
+    fx[g + n + 1:] = fx[g + n]
+    face[0][0, 0, :] = fx
+    for d in (1, 2):
+        col = np.concatenate([np.full(g, bc[0, d]), bc[:, d], np.full(g, bc[-1, d])]) * pf
+        face[d][0, 0, :] = col
+    s.face = face
+    if metric is not None:
+        s.metric = 1
+        s.alpha = np.full(s.shape, metric[0])
+        s.psi = np.full(s.shape, metric[1])
+    return s
+
+
 def steady_dynamo(n=128, k=1, eta=0.1, xi=0.5, rho=1e-14, p=1e-14, recon=MC, imex=SSP2, gamma=4.0 / 3.0):
     """1-D steady mean-field dynamo (Sec 5.7): periodic x in [-pi, pi], fluid
     at rest with the matter frozen, B^y = 0.1 sin(kx), B^z = -0.1 cos(kx),
