@@ -178,6 +178,20 @@ gr_status gr_con2prim(const gr_grid *grid, gr_state *state, hipStream_t stream);
  * Uses the workspace scratch; deterministic reduction order. */
 gr_status gr_divB_norm(const gr_grid *grid, const gr_state *state, double *out3_dev, hipStream_t stream);
 
+/* gr_divB_norm for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same norms, bit for bit, with the reduction partials in a file-scope
+ * device array of the library (3 x 4096 doubles = 96 KiB on every GPU the
+ * library runs on, held until the process ends) instead of the workspace;
+ * only grid, state->face and out3_dev are used (state->work may be NULL).
+ * Allocates nothing; the array's device address is looked up once per device
+ * (gr_init_state does it; otherwise the first call on that device).  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams) race and must be ordered by the caller.  GR_ENOMEM if
+ * the partials would not fit the array (no grid reaches it: the partial
+ * count is capped at 4096 blocks); otherwise errors as gr_divB_norm. */
+gr_status gr_divB_norm_noalloc(const gr_grid *grid, const gr_state *state, double *out3_dev, hipStream_t stream);
+
 /* Elliptic divergence cleaning of the face fields (Sec 3.3, eq. poisson and
  * eq. update_bfield): solve L Phi = div q_B on the interior cells with
  * `vcycles` multigrid V-cycles (red-black Gauss-Seidel 2+2, mean

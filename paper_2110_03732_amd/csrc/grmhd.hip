@@ -1495,6 +1495,60 @@ __global__ void __launch_bounds__(kBlock) k_stream_copy(const double2 *__restric
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free divergence norm: the reduction partials
+// (three per block, at most kMaxParts blocks) in a file-scope device array,
+// one copy per GPU the library runs on, held until the process ends.  Host
+// code uses only the device address looked up per device (the array's name
+// is a host-side stand-in there), never the name itself.
+constexpr int kScratchDoubles = 3 * kMaxParts;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device, looked up on the first
+// call per device (the library's init call, gr_init_state, does it first)
+gr_status scratch_ptr(double **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return GR_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return GR_EHIP;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GR_OK;
+}
+
+// the divergence norms (both entry points): partials into `part`, then the
+// fixed-order final reduction
+gr_status divb_norm_into(const gr_grid *g, const gr_state *st, double *part, double *out3, hipStream_t s)
+{
+    Geo G = make_geo(g);
+    FlatBox B = flatbox(G);
+    unsigned nb = nblocks(B.total);
+    if (g->glm) {
+        BcArgs Bc;
+        for (int d = 0; d < 3; d++)
+            for (int e = 0; e < 2; e++) Bc.bc[d][e] = g->bc[d][e];
+        hipLaunchKernelGGL(k_divb_cc_partial, dim3(nb), dim3(256), 0, s, G, B, Bc, cptrs<3>(st->face, G.fs), part);
+    } else {
+        hipLaunchKernelGGL(k_divb_partial, dim3(nb), dim3(256), 0, s, G, B, cptrs<3>(st->face, G.fs), part);
+    }
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (int)nb, B.total, 0, part, out3);
+    LAUNCHCHK();
+    return GR_OK;
+}
+}  // namespace
+
 // ===========================================================================
 extern "C" {
 
@@ -1633,6 +1687,9 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     if (v != GR_OK) return v;
     if (!prim_host || !E_host) return GR_EINVAL;
     if (g->metric && !metric_host) return GR_EINVAL;
+    double *scr = nullptr;
+    v = scratch_ptr(&scr);  // set-up of the allocation-free entry point on this device
+    if (v != GR_OK) return v;
     Geo G = make_geo(g);
     Phys P = make_phys(g);
     Tableau T = tableau(g->imex);
@@ -1795,22 +1852,20 @@ gr_status gr_divB_norm(const gr_grid *g, const gr_state *st, double *out3, hipSt
     v = check_state(g, st);
     if (v != GR_OK) return v;
     if (!out3) return GR_EINVAL;
-    Geo G = make_geo(g);
-    FlatBox B = flatbox(G);
-    unsigned nb = nblocks(B.total);
-    double *part = wparts(st);
-    if (g->glm) {
-        BcArgs Bc;
-        for (int d = 0; d < 3; d++)
-            for (int e = 0; e < 2; e++) Bc.bc[d][e] = g->bc[d][e];
-        hipLaunchKernelGGL(k_divb_cc_partial, dim3(nb), dim3(256), 0, s, G, B, Bc, cptrs<3>(st->face, G.fs), part);
-    } else {
-        hipLaunchKernelGGL(k_divb_partial, dim3(nb), dim3(256), 0, s, G, B, cptrs<3>(st->face, G.fs), part);
-    }
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (int)nb, B.total, 0, part, out3);
-    LAUNCHCHK();
-    return GR_OK;
+    return divb_norm_into(g, st, wparts(st), out3, s);
+}
+
+gr_status gr_divB_norm_noalloc(const gr_grid *g, const gr_state *st, double *out3, hipStream_t s)
+{
+    gr_status v = gr_validate(g);
+    if (v != GR_OK) return v;
+    if (!st || !st->face || !out3) return GR_EINVAL;  // only the face fields are read; work may be NULL
+    const Geo G = make_geo(g);
+    if (3 * (long)nblocks(flatbox(G).total) > kScratchDoubles) return GR_ENOMEM;  // partials beyond the array
+    double *part = nullptr;
+    v = scratch_ptr(&part);
+    if (v != GR_OK) return v;
+    return divb_norm_into(g, st, part, out3, s);
 }
 
 gr_status gr_clean_divB(const gr_grid *g, gr_state *st, int vcycles, double *out6, hipStream_t s)

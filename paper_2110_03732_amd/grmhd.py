@@ -20,7 +20,8 @@ EXPORTED = ["gr_abi_version", "gr_strerror", "gr_validate", "gr_field_stride", "
             "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim", "gr_divB_norm",
             "gr_cfl_dt", "gr_fail_count", "gr_timing_start", "gr_timing_read", "gr_kernel_class_name",
             "gr_clean_divB", "gr_batch_create", "gr_batch_update", "gr_batch_set_dt", "gr_batch_step", "gr_batch_run",
-            "gr_batch_stats", "gr_batch_tiles", "gr_tile_name", "gr_batch_destroy", "gr_stream_read", "gr_stream_copy"]
+            "gr_batch_stats", "gr_batch_tiles", "gr_tile_name", "gr_batch_destroy", "gr_stream_read", "gr_stream_copy",
+            "gr_divB_norm_noalloc"]
 
 
 class GrError(RuntimeError):
@@ -75,6 +76,7 @@ def lib():
         L.gr_step.argtypes = [G, S, ctypes.c_double, V]
         L.gr_con2prim.argtypes = [G, S, V]
         L.gr_divB_norm.argtypes = [G, S, V, V]
+        L.gr_divB_norm_noalloc.argtypes = [G, S, V, V]
         L.gr_clean_divB.argtypes = [G, S, ctypes.c_int, V, V]
         L.gr_clean_divB.restype = ctypes.c_int
         L.gr_cfl_dt.argtypes = [G, S, D, V]
@@ -100,7 +102,7 @@ def lib():
                      "gr_batch_stats", "gr_batch_tiles", "gr_batch_destroy", "gr_stream_read", "gr_stream_copy"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("gr_timing_start", "gr_timing_read", "gr_validate", "gr_workspace_offset", "gr_init_state", "gr_imex_stage", "gr_step", "gr_con2prim",
-                     "gr_divB_norm", "gr_cfl_dt", "gr_fail_count"):
+                     "gr_divB_norm", "gr_divB_norm_noalloc", "gr_cfl_dt", "gr_fail_count"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -170,6 +172,11 @@ def gr_con2prim(grid, state, stream):
 def gr_divB_norm(grid, state, out3_dev_ptr, stream):
     _chk(lib().gr_divB_norm(ctypes.byref(grid), ctypes.byref(state), ctypes.c_void_p(out3_dev_ptr),
                             ctypes.c_void_p(stream)))
+
+
+def gr_divB_norm_noalloc(grid, state, out3_dev_ptr, stream):
+    _chk(lib().gr_divB_norm_noalloc(ctypes.byref(grid), ctypes.byref(state), ctypes.c_void_p(out3_dev_ptr),
+                                    ctypes.c_void_p(stream)))
 
 
 def gr_clean_divB(grid, state, vcycles, out6_dev_ptr, stream):
