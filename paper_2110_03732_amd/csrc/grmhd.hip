@@ -240,7 +240,7 @@ struct Layout {
 // each coarser level halves every active direction while all of them are
 // even and stay >= 2.  Returns the number of levels and the doubles needed
 // (three compact arrays per level); fills lv when given.
-constexpr int kMgMaxLevels = 24;
+constexpr int kMgMaxLevels = kMgLevelsMax;  // the one-block kernel takes them all
 int mg_levels(const gr_grid *g, MgLevel *lv, double *base, size_t *doubles)
 {
     int n[3], act[3];
@@ -1897,23 +1897,47 @@ gr_status gr_clean_divB(const gr_grid *g, gr_state *st, int vcycles, double *out
     for (int d = 0; d < 3; d++) nmax = lv[nl - 1].n[d] > nmax ? lv[nl - 1].n[d] : nmax;
     const int coarse_sweeps = nmax * nmax > 512 ? 512 : (nmax * nmax < 4 ? 4 : nmax * nmax);
     auto smooth = [&](const MgLevel &L, int sweeps) -> gr_status {
+        const bool half = L.act[0] && L.n[0] % 2 == 0;  // one thread per cell of the color
+        const long cells = (long)L.n[0] * L.n[1] * L.n[2];
+        const dim3 hb((unsigned)((cells / 2 + 255) / 256));
         for (int i = 0; i < sweeps; i++)
             for (int col = 0; col < 2; col++) {
-                hipLaunchKernelGGL(k_mg_smooth, blocks(L), dim3(256), 0, s, L, col);
+                if (half) hipLaunchKernelGGL(k_mg_smooth_color, hb, dim3(256), 0, s, L, col);
+                else hipLaunchKernelGGL(k_mg_smooth, blocks(L), dim3(256), 0, s, L, col);
                 LAUNCHCHK();
             }
         return GR_OK;
     };
+    // levels from ls on are small enough for one workgroup: that part of
+    // each V-cycle is one launch (k_mg_small_cycle) instead of a launch per
+    // stage; the arithmetic and its order are the same
+    int ls = nl;
+    long small = 0;
+    while (ls > 0) {
+        const long c = (long)lv[ls - 1].n[0] * lv[ls - 1].n[1] * lv[ls - 1].n[2];
+        if (c > kMgOneBlockCells || small + c > kMgSmallCells) break;
+        small += c;
+        ls--;
+    }
+    MgStack stk;
+    for (int l = 0, off = 0; l < nl; l++) {
+        stk.lv[l] = lv[l];
+        stk.sh_off[l] = l >= ls ? off : 0;
+        if (l >= ls) off += 2 * lv[l].n[0] * lv[l].n[1] * lv[l].n[2];
+    }
     for (int cyc = 0; cyc < vcycles; cyc++) {
-        for (int l = 0; l < nl - 1; l++) {
+        for (int l = 0; l < ls && l < nl - 1; l++) {
             if ((v = smooth(lv[l], 2)) != GR_OK) return v;
-            hipLaunchKernelGGL(k_mg_residual, blocks(lv[l]), dim3(256), 0, s, lv[l]);
-            LAUNCHCHK();
             hipLaunchKernelGGL(k_mg_restrict, blocks(lv[l + 1]), dim3(256), 0, s, lv[l], lv[l + 1]);
             LAUNCHCHK();
         }
-        if ((v = smooth(lv[nl - 1], coarse_sweeps)) != GR_OK) return v;
-        for (int l = nl - 2; l >= 0; l--) {
+        if (ls < nl) {
+            hipLaunchKernelGGL(k_mg_small_cycle, dim3(1), dim3(kMgBlockThreads), 0, s, stk, ls, nl, coarse_sweeps);
+            LAUNCHCHK();
+        } else if ((v = smooth(lv[nl - 1], coarse_sweeps)) != GR_OK) {
+            return v;
+        }
+        for (int l = (ls < nl ? ls : nl - 1) - 1; l >= 0; l--) {
             hipLaunchKernelGGL(k_mg_prolong, blocks(lv[l]), dim3(256), 0, s, lv[l + 1], lv[l]);
             LAUNCHCHK();
             if ((v = smooth(lv[l], 2)) != GR_OK) return v;

@@ -196,7 +196,7 @@ __device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const C
 // threads of a block that owns a tile of n cells: whole wavefronts
 constexpr int tile_threads(int n) { return (n + 63) / 64 * 64; }
 
-template <int D, int T0, int T1, int T2, bool GLM = false>
+template <int D, int T0, int T1, int T2, bool GLM = false, bool PCELL = false>
 struct PhaseDims {
     static constexpr int NC = T0 * T1 * T2;  // cells of the tile
     static constexpr int NT = tile_threads(NC);
@@ -210,18 +210,27 @@ struct PhaseDims {
     static constexpr int FS = D == 0 ? 1 : (D == 1 ? F0 : F0 * F1);
     static constexpr int NV = NVar<GLM>::NV;
     static constexpr int NFL = NVar<GLM>::NF;
-    static constexpr int LDS = NV * NRAW;  // doubles
+    // PPM: the cells of the tile plus one on each side along D get their
+    // left and right interface values once (X0 x X1 x X2 box, stride XS
+    // along D), kept in LDS as 2 NV arrays for the faces to read
+    static constexpr int X0 = T0 + (D == 0 ? 2 : 0), X1 = T1 + (D == 1 ? 2 : 0), X2 = T2 + (D == 2 ? 2 : 0);
+    static constexpr int NE = X0 * X1 * X2;
+    static constexpr int XS = D == 0 ? 1 : (D == 1 ? X0 : X0 * X1);
+    static constexpr int LR = PCELL ? 2 * NV * NE : 0;
+    static constexpr int LDS = NV * NRAW > LR ? NV * NRAW : LR;  // doubles
     static_assert(NF <= 2 * NT, "at most two faces per thread");
-    static_assert(NFL * NF <= NV * NRAW, "fluxes fit in the staging buffer");
+    static_assert(NFL * NF <= LDS, "fluxes fit in the staging buffer");
 };
 
 // stage block of the sweeps: sp holds rho, u~, p, E (8) and with GLM Psi, Phi
 // (fields 8, 9); sf the face fields (GLM: cell-centred q_B)
-template <int REC, int MET, int D, int T0, int T1, int T2, bool GLM = false>
+// PCELL (PPM only): interface values per cell instead of per face
+template <int REC, int MET, int D, int T0, int T1, int T2, bool GLM = false, bool PCELL = false>
 __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const CPtr<10> &sp, const CPtr<3> &sf,
                                             const CPtr<2> &met, const int org[3], double *lds, double *Ld)
 {
-    using PD = PhaseDims<D, T0, T1, T2, GLM>;
+    static_assert(!PCELL || REC == GR_PPM, "per-cell interface values are a PPM form");
+    using PD = PhaseDims<D, T0, T1, T2, GLM, PCELL>;
     constexpr int NT = PD::NT, H = PD::H, E0 = PD::E0, E1 = PD::E1, NRAW = PD::NRAW, SD = PD::SD;
     constexpr int F0 = PD::F0, F1 = PD::F1, NF = PD::NF, NV = PD::NV, NFL = PD::NFL;
     constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
@@ -264,6 +273,45 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
     }
     __syncthreads();
 
+    // PPM: the left and right interface values of every cell of the tile and
+    // of one cell beyond it on each side along D, each cell once (two
+    // interface values and the monotonicity constraints of that cell): the
+    // same arithmetic as per face, where every interface value and every
+    // cell's constraints would be evaluated two or three times
+    constexpr int X0 = PD::X0, X1 = PD::X1, NE = PD::NE, XS = PD::XS;
+    double(*lr)[NE] = reinterpret_cast<double(*)[NE]>(lds);  // [v] aL, [NV + v] aR
+    if constexpr (PCELL) {
+        constexpr int NRE = (NE + NT - 1) / NT;
+        double cl[NRE][NV], cr[NRE][NV];
+#pragma unroll
+        for (int k = 0; k < NRE; k++) {
+            const int e = tid + k * NT;
+            if (e < NE) {
+                const int x[3] = {e % X0, (e / X0) % X1, e / (X0 * X1)};
+                // ext cell x_D = 0 is cell -1 of the tile, raw index H - 1 along D
+                const int r = (x[0] + (D == 0 ? H - 1 : 0)) +
+                              E0 * ((x[1] + (D == 1 ? H - 1 : 0)) + E1 * (x[2] + (D == 2 ? H - 1 : 0)));
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    recon_cell<REC>(raw[v][r - 2 * SD], raw[v][r - SD], raw[v][r], raw[v][r + SD], raw[v][r + 2 * SD],
+                                    cl[k][v], cr[k][v]);
+            }
+        }
+        __syncthreads();  // every raw value read: the buffer takes the interface values
+#pragma unroll
+        for (int k = 0; k < NRE; k++) {
+            const int e = tid + k * NT;
+            if (e < NE) {
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    lr[v][e] = cl[k][v];
+                    lr[NV + v][e] = cr[k][v];
+                }
+            }
+        }
+        __syncthreads();
+    }
+
     constexpr int NFR = (NF + NT - 1) / NT;  // faces per thread (1 or 2)
     double Fr[NFR][NFL];
 #pragma unroll
@@ -271,14 +319,25 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
         const int f = tid + k * NT;
         if (f >= NF) break;
         int e[3] = {f % F0, (f / F0) % F1, f / (F0 * F1)};
-        const int r0 = (e[0] + (D == 0 ? H : 0)) + E0 * ((e[1] + (D == 1 ? H : 0)) + E1 * (e[2] + (D == 2 ? H : 0)));
         double sL[NV], sR[NV];
+        if constexpr (PCELL) {
+            // face e_D lies between ext cells e_D (below) and e_D + 1 (above)
+            const int xb = e[0] + X0 * (e[1] + X1 * e[2]);
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
-            double w[6];
+            for (int v = 0; v < NV; v++) {
+                sL[v] = lr[NV + v][xb];   // right value of the cell below
+                sR[v] = lr[v][xb + XS];   // left value of the cell above
+            }
+        } else {
+            const int r0 =
+                (e[0] + (D == 0 ? H : 0)) + E0 * ((e[1] + (D == 1 ? H : 0)) + E1 * (e[2] + (D == 2 ? H : 0)));
 #pragma unroll
-            for (int m = 0; m < 6; m++) w[m] = raw[v][r0 + (m - 3) * SD];
-            recon_face<REC>(w, sL[v], sR[v]);
+            for (int v = 0; v < NV; v++) {
+                double w[6];
+#pragma unroll
+                for (int m = 0; m < 6; m++) w[m] = raw[v][r0 + (m - 3) * SD];
+                recon_face<REC>(w, sL[v], sR[v]);
+            }
         }
         int c[3] = {org[0] + e[0], org[1] + e[1], org[2] + e[2]};
 #pragma unroll
@@ -334,16 +393,22 @@ __device__ __forceinline__ void xy_body(const XyArgs &a, Blk blk)
     const Geo &G = a.G;
     // TY == 1 tiles serve 1-D grids only: no y phase, LDS for the x phase
     constexpr bool HASY = TY > 1;
-    constexpr int LX = PhaseDims<0, TX, TY, 1, GLM>::LDS, LY = HASY ? PhaseDims<1, TX, TY, 1, GLM>::LDS : 1;
+    // per-cell PPM interface values in a phase whose arrays fit 40 KiB of
+    // LDS (four blocks per compute unit); the other phase keeps the per-face
+    // form, so the block's LDS is not raised by the per-cell arrays
+    constexpr bool PCX = REC == GR_PPM && PhaseDims<0, TX, TY, 1, GLM, true>::LR * 8 <= 40960;
+    constexpr bool PCY = REC == GR_PPM && PhaseDims<1, TX, TY, 1, GLM, true>::LR * 8 <= 40960;
+    constexpr int LX = PhaseDims<0, TX, TY, 1, GLM, PCX>::LDS,
+                  LY = HASY ? PhaseDims<1, TX, TY, 1, GLM, PCY>::LDS : 1;
     constexpr int NFL = NVar<GLM>::NF;
     __shared__ double lds[LX > LY ? LX : LY];
     const unsigned bx = blk.x, by = blk.y, bz = blk.z;
     const int org[3] = {G.g[0] + (int)bx * TX, G.g[1] + (int)by * TY, G.g[2] + (int)bz};
     double L[NFL];
-    sweep_phase<REC, MET, 0, TX, TY, 1, GLM>(G, a.P, a.sp, a.sf, a.met, org, lds, L);
+    sweep_phase<REC, MET, 0, TX, TY, 1, GLM, PCX>(G, a.P, a.sp, a.sf, a.met, org, lds, L);
     if (HASY && G.act[1]) {
         double Ly[NFL];
-        sweep_phase<REC, MET, 1, TX, TY, 1, GLM>(G, a.P, a.sp, a.sf, a.met, org, lds, Ly);
+        sweep_phase<REC, MET, 1, TX, TY, 1, GLM, PCY>(G, a.P, a.sp, a.sf, a.met, org, lds, Ly);
 #pragma unroll
         for (int v = 0; v < NFL; v++) L[v] += Ly[v];
     }
@@ -1095,7 +1160,10 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     int c[3];
     double Lz[NQ];
     if constexpr (SWZ == 1) {
-        __shared__ double lds[PhaseDims<2, TX, 1, TZ, GLM>::LDS];
+        // the z phase takes the per-cell PPM form (the cell pass is held to
+        // three waves per SIMD by its registers, not by this LDS)
+        constexpr bool PCZ = REC == GR_PPM;
+        __shared__ double lds[PhaseDims<2, TX, 1, TZ, GLM, PCZ>::LDS];
         const int org[3] = {R.lo[0] + (int)blk.x * TX, R.lo[1] + (int)blk.y, R.lo[2] + (int)blk.z * TZ};
         CPtr<10> sp;
         CPtr<3> sf;
@@ -1107,7 +1175,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         met.p[0] = io.met[0];
         met.p[1] = io.met[1];
         static_assert(PhaseDims<2, TX, 1, TZ, GLM>::NT == kBlock, "z-phase tile of one block");
-        sweep_phase<REC, MET, 2, TX, 1, TZ, GLM>(G, P, sp, sf, met, org, lds, Lz);
+        sweep_phase<REC, MET, 2, TX, 1, TZ, GLM, PCZ>(G, P, sp, sf, met, org, lds, Lz);
         if ((int)threadIdx.x >= TX * TZ) return;  // beyond the tile
         c[0] = org[0] + (int)threadIdx.x % TX;
         c[1] = org[1];
