@@ -154,7 +154,12 @@ gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim
  * tableau needs it, then accumulates q* and solves the stiff Ohm's-law
  * update fused with the primitive recovery, Sec 2.4); pass p = s is the
  * final combination followed by the recovery with E and B known (Sec 2.6).
- * s = 2 for GR_SSP2_222, 4 for GR_SSP3_433.  Passes must run in order. */
+ * s = 2 for GR_SSP2_222, 4 for GR_SSP3_433.  Passes must run in order.
+ * In a pass that evaluates L, the edge-EMF and face-update launches run on a
+ * second stream the library owns (one per device, default priority, created
+ * by gr_init_state), forked from `stream` with an event after the ghost fill
+ * and joined back before the cell pass: the call stays ordered on `stream`
+ * and can be captured into a graph from it. */
 gr_status gr_imex_stage(const gr_grid *grid, gr_state *state, int pass, double dt, hipStream_t stream);
 
 /* All passes of one step (Sec 2.3).  Where passes 0 and 1 are both

@@ -844,6 +844,21 @@ void launch_cell(const Variant &V, int swz, const CellArgs &a, hipStream_t s)
     });
 }
 
+// a second stream per device for the edge-EMF and face-update launches of a
+// pass, which run beside the x/y sweeps (default priority, created once)
+std::mutex g_side_mu;
+hipStream_t g_side[64] = {};
+gr_status side_stream(hipStream_t *out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return GR_EHIP;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (!g_side[dev]) HIPCHK(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
+    *out = g_side[dev];
+    return GR_OK;
+}
+
 gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
 {
     if (pl.ghost) {
@@ -851,21 +866,56 @@ gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
         hipLaunchKernelGGL(k_ghost_all, d3(pl.gh.gd), dim3(kBlock), 0, s, pl.gh);
         LAUNCHCHK();
     }
+    // The EMFs and the face update depend on the ghost fill only, the x/y
+    // sweeps too: with both present the EMFs and the face update go to the
+    // side stream (forked after the ghost fill) and the cell pass waits for
+    // them, so the memory-bound face update overlaps the sweeps.
+    bool ct_any = pl.face;
+    for (int i = 0; i < 3; i++) ct_any |= pl.ct[i] != 0;
+    hipStream_t s2 = s;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (pl.xy && ct_any) {
+        gr_status e = side_stream(&s2);
+        if (e != GR_OK) return e;
+        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+            (void)hipEventDestroy(fork);
+            return GR_EHIP;
+        }
+        if (hipEventRecord(fork, s) != hipSuccess || hipStreamWaitEvent(s2, fork, 0) != hipSuccess) {
+            (void)hipEventDestroy(fork);
+            (void)hipEventDestroy(join);
+            return GR_EHIP;
+        }
+    }
+    for (int i = 0; i < 3; i++) {
+        if (!pl.ct[i]) continue;
+        TScope ts(KC_CT, s2, pl.ct_bytes[i]);
+        launch_ct(V, kCtOrder[i], pl.ctf[i], pl.cta[i], s2);
+        LAUNCHCHK();
+    }
+    if (pl.face) {
+        TScope ts(KC_FACE_UPDATE, s2, pl.fa_bytes);
+        hipLaunchKernelGGL(k_face_update, d3(pl.fa.gd), dim3(kBlock), 0, s2, pl.fa);
+        LAUNCHCHK();
+    }
+    if (join) {
+        const bool ok = hipEventRecord(join, s2) == hipSuccess;
+        (void)hipEventDestroy(fork);
+        if (!ok) {
+            (void)hipEventDestroy(join);
+            return GR_EHIP;
+        }
+    }
     if (pl.xy) {
         TScope ts(KC_SWEEP, s, pl.xy_bytes);
         launch_xy(V, pl.xya, s);
         LAUNCHCHK();
     }
-    for (int i = 0; i < 3; i++) {
-        if (!pl.ct[i]) continue;
-        TScope ts(KC_CT, s, pl.ct_bytes[i]);
-        launch_ct(V, kCtOrder[i], pl.ctf[i], pl.cta[i], s);
-        LAUNCHCHK();
-    }
-    if (pl.face) {
-        TScope ts(KC_FACE_UPDATE, s, pl.fa_bytes);
-        hipLaunchKernelGGL(k_face_update, d3(pl.fa.gd), dim3(kBlock), 0, s, pl.fa);
-        LAUNCHCHK();
+    if (join) {
+        const bool ok = hipStreamWaitEvent(s, join, 0) == hipSuccess;
+        (void)hipEventDestroy(join);
+        if (!ok) return GR_EHIP;
     }
     {
         TScope ts(KC_CELL_UPDATE, s, pl.ca_bytes);
@@ -1689,6 +1739,9 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     if (g->metric && !metric_host) return GR_EINVAL;
     double *scr = nullptr;
     v = scratch_ptr(&scr);  // set-up of the allocation-free entry point on this device
+    if (v != GR_OK) return v;
+    hipStream_t side = nullptr;
+    v = side_stream(&side);  // created here, so that a step under graph capture never creates it
     if (v != GR_OK) return v;
     Geo G = make_geo(g);
     Phys P = make_phys(g);
