@@ -204,8 +204,8 @@ __global__ void __launch_bounds__(256) k_mg_prolong(MgLevel C, MgLevel F)
 // levels live in LDS for the launch (level l0's are read in first and its
 // Phi written back at the end), so every stage runs at LDS latency.
 constexpr int kMgBlockThreads = 1024;
-constexpr int kMgOneBlockCells = 4096;  // levels at most this large run in the one-block kernel
-constexpr int kMgSmallCells = 2 * kMgOneBlockCells;  // all of them together (at most 4096 + 2048 + ... in 1-D)
+constexpr int kMgOneBlockCells = 512;  // levels at most this large run in the one-block kernel
+constexpr int kMgSmallCells = 2 * kMgOneBlockCells;  // all of them together (at most 512 + 256 + ... in 1-D)
 constexpr int kMgLevelsMax = 24;
 struct MgStack {
     MgLevel lv[kMgLevelsMax];
