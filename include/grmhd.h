@@ -155,11 +155,12 @@ gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim
  * update fused with the primitive recovery, Sec 2.4); pass p = s is the
  * final combination followed by the recovery with E and B known (Sec 2.6).
  * s = 2 for GR_SSP2_222, 4 for GR_SSP3_433.  Passes must run in order.
- * In a pass that evaluates L, the edge-EMF and face-update launches run on a
- * second stream the library owns (one per device, default priority, created
- * by gr_init_state), forked from `stream` with an event after the ghost fill
- * and joined back before the cell pass: the call stays ordered on `stream`
- * and can be captured into a graph from it. */
+ * In a pass that evaluates L on a grid of at least 2^20 interior cells, the
+ * edge-EMF and face-update launches run on a second stream the library owns
+ * (one per device, default priority, created by gr_init_state), forked from
+ * `stream` with an event after the ghost fill and joined back before the cell
+ * pass: the call stays ordered on `stream` and can be captured into a graph
+ * from it.  Smaller grids launch everything on `stream`. */
 gr_status gr_imex_stage(const gr_grid *grid, gr_state *state, int pass, double dt, hipStream_t stream);
 
 /* All passes of one step (Sec 2.3).  Where passes 0 and 1 are both
@@ -285,7 +286,10 @@ gr_status gr_batch_set_dt(gr_batch *batch, const double *dt, hipStream_t stream)
 gr_status gr_batch_update(gr_batch *batch, const gr_grid *grids, const gr_state *states, const double *dt,
                           int nruns, hipStream_t stream);
 
-/* One step of every run, launched eagerly on the stream. */
+/* One step of every run, launched eagerly on the stream.  When the runs
+ * hold at least 2^20 interior cells together, the EMF and face-update
+ * launches of each pass run on the library's second stream beside the x/y
+ * sweeps, as in gr_imex_stage. */
 gr_status gr_batch_step(gr_batch *batch, hipStream_t stream);
 
 /* nsteps steps of every run: on the first call the step is captured into a

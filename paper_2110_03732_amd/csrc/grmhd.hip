@@ -530,8 +530,16 @@ void with_ct(int K, int F, Fn &&f)
 
 // Everything one pass of one run launches, in launch order: ghost fill,
 // x/y phases, the three EMF components, the face update, the cell pass.
+// a pass forks its EMF and face-update launches to the side stream only on
+// grids of at least this many cells: on smaller ones the two extra stream
+// dependencies cost more than the overlap gains (a 512^2 plane ran 8% slower
+// with the fork, and small grids on several caller streams would all queue on
+// the one side stream)
+constexpr long kForkCells = 1L << 20;
+
 struct PassPlan {
     bool ghost = false, xy = false, face = false;
+    bool fork = false;  // EMFs and face update beside the sweeps
     bool swz = false;  // cell pass with the z phase
     bool ct[3] = {false, false, false};
     int ctf[3] = {CT_BOX, CT_BOX, CT_BOX};  // EMF kernel form per launch
@@ -561,6 +569,7 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     Tableau T = tableau(g->imex);
     Layout Ly = layout(g);
     if (p < 0 || p > T.s) return GR_EINVAL;
+    pl.fork = (long)G.n[0] * G.n[1] * G.n[2] >= kForkCells;
     const int MET = V.met;
     const bool fin = (p == T.s);
     const bool withL = (p >= 1) && needL(T, p - 1);
@@ -874,7 +883,7 @@ gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
     for (int i = 0; i < 3; i++) ct_any |= pl.ct[i] != 0;
     hipStream_t s2 = s;
     hipEvent_t fork = nullptr, join = nullptr;
-    if (pl.xy && ct_any) {
+    if (pl.fork && pl.xy && ct_any) {
         gr_status e = side_stream(&s2);
         if (e != GR_OK) return e;
         HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
@@ -1327,12 +1336,67 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
     return GR_OK;
 }
 
-gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s)
+// The list holds, per pass, ghost fills, then x/y sweeps, EMFs and the face
+// update (which all depend on the ghost fill only), then the cell launches.
+// With forks (a batch of at least kForkCells cells), as in the plain path,
+// where a pass has both sweeps and EMF / face-update launches, the latter go
+// to the side stream, forked after the ghost fill, and the cell launches wait
+// for them.
+gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, bool forks)
 {
-    for (const auto &L : ls) {
-        TScope ts(L.cls, s, L.bytes);
-        gr_status e = launch_b(L, s);
+    auto one = [](const BLaunch &L, hipStream_t st) {
+        TScope ts(L.cls, st, L.bytes);
+        return launch_b(L, st);
+    };
+    auto side = [](int c) { return c == KC_CT || c == KC_FACE_UPDATE; };
+    const size_t n = ls.size();
+    size_t i = 0;
+    while (i < n) {
+        if (ls[i].cls != KC_SWEEP && !side(ls[i].cls)) {
+            gr_status e = one(ls[i++], s);
+            if (e != GR_OK) return e;
+            continue;
+        }
+        size_t j = i;
+        bool sw = false, sd = false;
+        for (; j < n && (ls[j].cls == KC_SWEEP || side(ls[j].cls)); j++) {
+            sw |= ls[j].cls == KC_SWEEP;
+            sd |= side(ls[j].cls);
+        }
+        hipStream_t s2 = s;
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (forks && sw && sd) {
+            gr_status e = side_stream(&s2);
+            if (e != GR_OK) return e;
+            HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+            if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+                (void)hipEventDestroy(fork);
+                return GR_EHIP;
+            }
+            const bool ok = hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(s2, fork, 0) == hipSuccess;
+            (void)hipEventDestroy(fork);
+            if (!ok) {
+                (void)hipEventDestroy(join);
+                return GR_EHIP;
+            }
+        }
+        gr_status e = GR_OK;
+        for (size_t k = i; k < j && e == GR_OK; k++)
+            if (side(ls[k].cls)) e = one(ls[k], s2);
+        if (join) {
+            // the join is recorded and waited for even after a failed launch,
+            // so the side stream never runs ahead of the launch stream
+            const bool ok = hipEventRecord(join, s2) == hipSuccess;
+            if (e == GR_OK && !ok) e = GR_EHIP;
+        }
+        for (size_t k = i; k < j && e == GR_OK; k++)
+            if (ls[k].cls == KC_SWEEP) e = one(ls[k], s);
+        if (join) {
+            if (hipStreamWaitEvent(s, join, 0) != hipSuccess && e == GR_OK) e = GR_EHIP;
+            (void)hipEventDestroy(join);
+        }
         if (e != GR_OK) return e;
+        i = j;
     }
     return GR_OK;
 }
@@ -1397,9 +1461,9 @@ double time_list(const std::vector<BLaunch> &ls, hipStream_t s, int reps)
         return -1.0;
     }
     double ms = -1.0;
-    if (launch_list(ls, s) == GR_OK && hipEventRecord(a, s) == hipSuccess) {
+    if (launch_list(ls, s, false) == GR_OK && hipEventRecord(a, s) == hipSuccess) {
         bool ok = true;
-        for (int i = 0; i < reps && ok; i++) ok = launch_list(ls, s) == GR_OK;
+        for (int i = 0; i < reps && ok; i++) ok = launch_list(ls, s, false) == GR_OK;
         float f = 0.0f;
         if (ok && hipEventRecord(e, s) == hipSuccess && hipEventSynchronize(e) == hipSuccess &&
             hipEventElapsedTime(&f, a, e) == hipSuccess)
@@ -2097,6 +2161,9 @@ gr_status gr_batch_create(gr_batch **out, const gr_grid *grids, const gr_state *
         if (!(dt[r] > 0.0)) return GR_EINVAL;
         if (grids[r].imex != grids[0].imex) return GR_EUNSUPPORTED;
     }
+    hipStream_t side;
+    gr_status v = side_stream(&side);  // created here, never under graph capture
+    if (v != GR_OK) return v;
     gr_batch *b = new (std::nothrow) gr_batch;
     if (!b) return GR_ENOMEM;
     b->grids.assign(grids, grids + nruns);
@@ -2164,7 +2231,7 @@ gr_status gr_batch_update(gr_batch *b, const gr_grid *grids, const gr_state *sta
 gr_status gr_batch_step(gr_batch *b, hipStream_t s)
 {
     if (!b) return GR_EINVAL;
-    return launch_list(b->launches, s);
+    return launch_list(b->launches, s, b->cells >= kForkCells);
 }
 
 gr_status gr_batch_run(gr_batch *b, int nsteps, hipStream_t s)
@@ -2176,7 +2243,7 @@ gr_status gr_batch_run(gr_batch *b, int nsteps, hipStream_t s)
         hipError_t c = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         gr_status e = GR_OK;
         if (c == hipSuccess) {
-            e = launch_list(b->launches, b->cap);
+            e = launch_list(b->launches, b->cap, b->cells >= kForkCells);
             c = hipStreamEndCapture(b->cap, &b->graph);
         }
         g_capturing = false;
