@@ -239,3 +239,46 @@ def test_batch_autotuner_cache(tmp_path):
         assert b2.tiles(i) == b.tiles(i)
     b.close()
     b2.close()
+
+
+def test_batch_with_side_stream_fork():
+    """a batch holding at least 2^20 cells runs the EMF and face-update
+    launches of each pass on the library's second stream beside the x/y
+    sweeps: its runs equal the same runs advanced alone (each below 2^20
+    cells, so launched on one stream) to 1e-13 of each field's scale with the
+    same failure counts, graph replays equal eager steps bit for bit, and the
+    star matches the oracle"""
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd
+    setups = [W.blast_wave(768, eta=1e-6), W.tov_star(64), W.blast_wave(512, eta=1e-2)]
+    assert sum(s.ncells for s in setups) >= 1 << 20
+    assert all(s.ncells < 1 << 20 for s in setups)
+    say("forked batch: %s" % [s.ncells for s in setups])
+    ra = [grmhd.Run(s, device="cuda:0") for s in setups]
+    rb = [grmhd.Run(s, device="cuda:0") for s in setups]
+    alone = [grmhd.Run(s, device="cuda:0") for s in setups]
+    dts = [r.dt() for r in ra]
+    ba = grmhd.Batch(ra, dts)
+    bb = grmhd.Batch(rb, dts)
+    for _ in range(3):
+        ba.step()
+    bb.run(3)
+    for r, dt in zip(alone, dts):
+        for _ in range(3):
+            r.step(dt)
+    torch.cuda.synchronize()
+    for x, y, z in zip(ra, rb, alone):
+        _same(x, y)
+        _close(x, z)
+        assert x.fail_count() == z.fail_count()
+    s = setups[1]
+    ref = oracle.OracleState(s)
+    for _ in range(3):
+        ref.step(dts[1])
+    r = ra[1]
+    errs = state_errors(s, r.prims(), ref.prim, device_E(r), oracle_E(ref), r.faces(), ref.face)
+    bad = [e for e in errs if not (e[1] <= 1e-10 and e[2] <= 1e-9)]
+    assert not bad, bad
+    assert r.fail_count() == ref.nfail
+    ba.close()
+    bb.close()
