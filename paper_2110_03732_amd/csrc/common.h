@@ -105,9 +105,21 @@ __device__ __forceinline__ int lin(const Geo &G, const int c[3])
 
 // loads / stores at a 32-bit byte offset from a uniform base pointer: the
 // address is formed by the memory instruction (scalar base + vector offset)
-// instead of a 64-bit vector add per pointer
-__device__ __forceinline__ double ldb(const double *p, unsigned off) { return *(const double *)((const char *)p + off); }
-__device__ __forceinline__ void stb(double *p, unsigned off, double v) { *(double *)((char *)p + off) = v; }
+// instead of a 64-bit vector add per pointer.  Every array these kernels
+// touch through them is device global memory; the pointer is taken into the
+// global address space explicitly, so that pointers read from memory (the
+// batched kernels' argument arrays) give global instead of flat loads and
+// stores, as kernel arguments do.
+typedef const __attribute__((address_space(1))) char g_cchar;
+typedef __attribute__((address_space(1))) char g_char;
+__device__ __forceinline__ double ldb(const double *p, unsigned off)
+{
+    return *(const __attribute__((address_space(1))) double *)((g_cchar *)p + off);
+}
+__device__ __forceinline__ void stb(double *p, unsigned off, double v)
+{
+    *(__attribute__((address_space(1))) double *)((g_char *)p + off) = v;
+}
 
 // reciprocal: hardware estimate refined by two Newton-Raphson steps
 // r <- r + r (1 - x r); for the positive, bounded denominators of the
