@@ -1539,9 +1539,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PAI
 {
     cell_body<REC, MET, SWZ, TX, TZ, XI, GLM, PAIR>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));
 }
-// the batched form reads its arguments through a pointer, which costs the
-// z-phase instance a few registers: it is held to the plain form's 3 waves per
-// SIMD (at the price of a few spilled registers)
+// the batched form reads its arguments through a pointer; it is held to the
+// plain form's 3 waves per SIMD (both take 166 VGPRs for the z-phase instance)
 template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM, bool PAIR = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((SWZ || PAIR) && !XI && !GLM ? 3 : 1)))
     kb_cell_update(const CellArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
