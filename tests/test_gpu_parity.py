@@ -362,6 +362,28 @@ def test_full_size_hundred_steps_parity(name):
     assert run.fail_count() == ref.nfail
 
 
+@pytest.mark.timeout(600)
+def test_full_size_star_twenty_steps_parity():
+    """20 steps of the 128^3 star, the benchmark's own step and launch
+    configuration (at 2^21 cells every pass runs its EMF and face-update
+    launches on the library's second stream), element by element against the
+    oracle at the multi-step bar"""
+    _torch()
+    s = W.tov_star(128)
+    say("128^3 star, 20 steps vs oracle")
+    run = gpu_run(s)
+    ref = oracle.OracleState(s)
+    dt = ref.dt()
+    for k in range(20):
+        run.step(dt)
+        ref.step(dt)
+        if k % 5 == 4:
+            say("  step %d" % (k + 1))
+    check(s, run, ref, *HUNDRED)
+    assert run.divB()[2] <= 1e-12
+    assert run.fail_count() == ref.nfail
+
+
 def test_shock_tube_to_t04_parity():
     """the 400-cell shock tube of its configuration run to t = 0.4 (400
     steps of dt = 1e-3) against the oracle"""
