@@ -160,7 +160,10 @@ gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim
  * (one per device, default priority, created by gr_init_state), forked from
  * `stream` with an event after the ghost fill and joined back before the cell
  * pass: the call stays ordered on `stream` and can be captured into a graph
- * from it.  Smaller grids launch everything on `stream`. */
+ * from it.  Smaller grids launch everything on `stream`.  The second stream
+ * is shared by every call on the device: forked calls from several host
+ * threads queue their EMF launches on it one after another, and a call being
+ * captured must not overlap a forked call from another thread. */
 gr_status gr_imex_stage(const gr_grid *grid, gr_state *state, int pass, double dt, hipStream_t stream);
 
 /* All passes of one step (Sec 2.3).  Where passes 0 and 1 are both
@@ -261,7 +264,8 @@ typedef struct gr_batch gr_batch;
  * does the same for the classes not yet listed in that text file and
  * appends its decisions to it.  Allocates the argument block (hipMalloc,
  * with spare room for later updates) and its pinned host staging
- * (hipHostMalloc), and synchronises the stream.  GR_EUNSUPPORTED if the runs
+ * (hipHostMalloc) and a second stream for the forked launches of
+ * gr_batch_step, and synchronises the stream.  GR_EUNSUPPORTED if the runs
  * mix IMEX tableaux. */
 gr_status gr_batch_create(gr_batch **batch, const gr_grid *grids, const gr_state *states, const double *dt,
                           int nruns, const char *tune_cache, hipStream_t stream);
@@ -288,8 +292,9 @@ gr_status gr_batch_update(gr_batch *batch, const gr_grid *grids, const gr_state 
 
 /* One step of every run, launched eagerly on the stream.  When the runs
  * hold at least 2^20 interior cells together, the EMF and face-update
- * launches of each pass run on the library's second stream beside the x/y
- * sweeps, as in gr_imex_stage. */
+ * launches of each pass run on a second stream the batch owns (created by
+ * gr_batch_create, default priority) beside the x/y sweeps, forked from and
+ * joined back into `stream` as in gr_imex_stage. */
 gr_status gr_batch_step(gr_batch *batch, hipStream_t stream);
 
 /* nsteps steps of every run: on the first call the step is captured into a
@@ -308,9 +313,10 @@ gr_status gr_batch_stats(const gr_batch *batch, int *launches_per_step, double *
 gr_status gr_batch_tiles(const gr_batch *batch, int run, int *xy_tile, int *cz_tile);
 const char *gr_tile_name(int which, int tile);
 
-/* Free the batch (argument block, staging buffers and graph).  Waits for
- * the batch's own argument copies; otherwise does not synchronise: the
- * caller makes sure no launch of the batch is still pending. */
+/* Free the batch (argument block, staging buffers, graph and its streams).
+ * Waits for the batch's own argument copies and its second stream;
+ * otherwise does not synchronise: the caller makes sure no launch of the
+ * batch is still pending. */
 gr_status gr_batch_destroy(gr_batch *batch);
 
 /* Measurement hooks (not part of the method): a streaming read of `bytes`

@@ -1027,6 +1027,7 @@ struct gr_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
+    hipStream_t side = nullptr;  // the batch's own stream for the EMF and face-update launches
     double bytes_step = 0.0;
     long cells = 0;
 };
@@ -1338,36 +1339,35 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
 
 // The list holds, per pass, ghost fills, then x/y sweeps, EMFs and the face
 // update (which all depend on the ghost fill only), then the cell launches.
-// With forks (a batch of at least kForkCells cells), as in the plain path,
-// where a pass has both sweeps and EMF / face-update launches, the latter go
-// to the side stream, forked after the ghost fill, and the cell launches wait
-// for them.
-gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, bool forks)
+// With a side stream (a batch of at least kForkCells cells), as in the plain
+// path, where a pass has both sweeps and EMF / face-update launches, the
+// latter go to the side stream, forked after the ghost fill, and the cell
+// launches wait for them.  side == nullptr: everything on s.
+gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, hipStream_t side)
 {
     auto one = [](const BLaunch &L, hipStream_t st) {
         TScope ts(L.cls, st, L.bytes);
         return launch_b(L, st);
     };
-    auto side = [](int c) { return c == KC_CT || c == KC_FACE_UPDATE; };
+    auto on_side = [](int c) { return c == KC_CT || c == KC_FACE_UPDATE; };
     const size_t n = ls.size();
     size_t i = 0;
     while (i < n) {
-        if (ls[i].cls != KC_SWEEP && !side(ls[i].cls)) {
+        if (ls[i].cls != KC_SWEEP && !on_side(ls[i].cls)) {
             gr_status e = one(ls[i++], s);
             if (e != GR_OK) return e;
             continue;
         }
         size_t j = i;
         bool sw = false, sd = false;
-        for (; j < n && (ls[j].cls == KC_SWEEP || side(ls[j].cls)); j++) {
+        for (; j < n && (ls[j].cls == KC_SWEEP || on_side(ls[j].cls)); j++) {
             sw |= ls[j].cls == KC_SWEEP;
-            sd |= side(ls[j].cls);
+            sd |= on_side(ls[j].cls);
         }
         hipStream_t s2 = s;
         hipEvent_t fork = nullptr, join = nullptr;
-        if (forks && sw && sd) {
-            gr_status e = side_stream(&s2);
-            if (e != GR_OK) return e;
+        if (side && sw && sd) {
+            s2 = side;
             HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
             if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
                 (void)hipEventDestroy(fork);
@@ -1382,7 +1382,7 @@ gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, bool forks)
         }
         gr_status e = GR_OK;
         for (size_t k = i; k < j && e == GR_OK; k++)
-            if (side(ls[k].cls)) e = one(ls[k], s2);
+            if (on_side(ls[k].cls)) e = one(ls[k], s2);
         if (join) {
             // the join is recorded and waited for even after a failed launch,
             // so the side stream never runs ahead of the launch stream
@@ -1461,9 +1461,9 @@ double time_list(const std::vector<BLaunch> &ls, hipStream_t s, int reps)
         return -1.0;
     }
     double ms = -1.0;
-    if (launch_list(ls, s, false) == GR_OK && hipEventRecord(a, s) == hipSuccess) {
+    if (launch_list(ls, s, nullptr) == GR_OK && hipEventRecord(a, s) == hipSuccess) {
         bool ok = true;
-        for (int i = 0; i < reps && ok; i++) ok = launch_list(ls, s, false) == GR_OK;
+        for (int i = 0; i < reps && ok; i++) ok = launch_list(ls, s, nullptr) == GR_OK;
         float f = 0.0f;
         if (ok && hipEventRecord(e, s) == hipSuccess && hipEventSynchronize(e) == hipSuccess &&
             hipEventElapsedTime(&f, a, e) == hipSuccess)
@@ -2161,11 +2161,13 @@ gr_status gr_batch_create(gr_batch **out, const gr_grid *grids, const gr_state *
         if (!(dt[r] > 0.0)) return GR_EINVAL;
         if (grids[r].imex != grids[0].imex) return GR_EUNSUPPORTED;
     }
-    hipStream_t side;
-    gr_status v = side_stream(&side);  // created here, never under graph capture
-    if (v != GR_OK) return v;
     gr_batch *b = new (std::nothrow) gr_batch;
     if (!b) return GR_ENOMEM;
+    if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess) {
+        b->side = nullptr;
+        delete b;
+        return GR_EHIP;
+    }
     b->grids.assign(grids, grids + nruns);
     b->states.assign(states, states + nruns);
     b->dt.assign(dt, dt + nruns);
@@ -2231,7 +2233,7 @@ gr_status gr_batch_update(gr_batch *b, const gr_grid *grids, const gr_state *sta
 gr_status gr_batch_step(gr_batch *b, hipStream_t s)
 {
     if (!b) return GR_EINVAL;
-    return launch_list(b->launches, s, b->cells >= kForkCells);
+    return launch_list(b->launches, s, b->cells >= kForkCells ? b->side : nullptr);
 }
 
 gr_status gr_batch_run(gr_batch *b, int nsteps, hipStream_t s)
@@ -2243,7 +2245,7 @@ gr_status gr_batch_run(gr_batch *b, int nsteps, hipStream_t s)
         hipError_t c = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         gr_status e = GR_OK;
         if (c == hipSuccess) {
-            e = launch_list(b->launches, b->cap, b->cells >= kForkCells);
+            e = launch_list(b->launches, b->cap, b->cells >= kForkCells ? b->side : nullptr);
             c = hipStreamEndCapture(b->cap, &b->graph);
         }
         g_capturing = false;
@@ -2288,6 +2290,7 @@ gr_status gr_batch_destroy(gr_batch *b)
 {
     if (!b) return GR_OK;
     drop_graph(b);
+    if (b->side) (void)hipStreamSynchronize(b->side);  // its launches read the argument block
     if (b->dev) (void)hipFree(b->dev);
     for (int h = 0; h < 2; h++) {
         if (b->host_ev[h]) {
@@ -2297,6 +2300,7 @@ gr_status gr_batch_destroy(gr_batch *b)
         if (b->host[h]) (void)hipHostFree(b->host[h]);
     }
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
     return GR_OK;
 }
