@@ -1816,12 +1816,12 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     Region Rall = region(G, 0, 7);
     dim3 gr, bl;
     launch_dims(Rall, gr, bl);
-    double *scratch = wfield(st, G, Ly.L);  // the stored-L block (>= 22 fields) is free before the first step
-    // host fields are compact: one contiguous copy into scratch, then spread
+    double *staging = wfield(st, G, Ly.L);  // the stored-L block (>= 22 fields) is free before the first step
+    // host fields are compact: one contiguous copy into staging, then spread
     // into the padded rows of the device layout
     auto put = [&](double *field, const double *host) -> gr_status {
-        HIPCHK(hipMemcpyAsync(scratch, host, cb, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_unpack, gr, bl, 0, s, G, scratch, field);
+        HIPCHK(hipMemcpyAsync(staging, host, cb, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_unpack, gr, bl, 0, s, G, staging, field);
         LAUNCHCHK();
         return GR_OK;
     };
@@ -1845,11 +1845,11 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     double *Ad = nullptr, *fd = nullptr;
     if (A_host) {
         if ((size_t)3 * es > (size_t)12 * G.fs) return GR_EINVAL;
-        Ad = scratch;
+        Ad = staging;
         HIPCHK(hipMemcpyAsync(Ad, A_host, 3 * es * sizeof(double), hipMemcpyHostToDevice, s));
     }
     if (face_host) {
-        fd = scratch + (size_t)12 * G.fs;
+        fd = staging + (size_t)12 * G.fs;
         HIPCHK(hipMemcpyAsync(fd, face_host, 3 * cb, hipMemcpyHostToDevice, s));
     }
     hipLaunchKernelGGL(k_curlA, gr, bl, 0, s, G, Ne0, Ne1, Ad, es, fd, np, ptrs<3>(st->face, G.fs));
@@ -1866,8 +1866,8 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
     LAUNCHCHK();
     if (g->glm) {
         // cell-centred q_B from the faces; q_Psi = q_Phi = 0
-        HIPCHK(hipMemcpyAsync(scratch, st->face, 3 * G.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(k_face_to_cell, gr, bl, 0, s, G, cptrs<3>(scratch, G.fs), ptrs<3>(st->face, G.fs));
+        HIPCHK(hipMemcpyAsync(staging, st->face, 3 * G.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_face_to_cell, gr, bl, 0, s, G, cptrs<3>(staging, G.fs), ptrs<3>(st->face, G.fs));
         LAUNCHCHK();
         HIPCHK(hipMemsetAsync(st->q + 8 * G.fs, 0, 2 * G.fs * sizeof(double), s));
     }
