@@ -280,5 +280,20 @@ def test_batch_with_side_stream_fork():
     bad = [e for e in errs if not (e[1] <= 1e-10 and e[2] <= 1e-9)]
     assert not bad, bad
     assert r.fail_count() == ref.nfail
+    # a membership update that takes the batch below 2^20 cells (its passes
+    # then launch on one stream), then back above it
+    small = [ra[0], ra[1]]
+    assert sum(x.setup.ncells for x in small) < 1 << 20
+    ba.update(small, dts[:2])
+    ba.step()
+    ba.update(ra, dts)
+    ba.step()
+    for i, z in enumerate(alone):
+        for _ in range(2 if i < 2 else 1):
+            z.step(dts[i])
+    torch.cuda.synchronize()
+    for x, z in zip(ra, alone):
+        _close(x, z)
+        assert x.fail_count() == z.fail_count()
     ba.close()
     bb.close()
