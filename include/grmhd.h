@@ -139,12 +139,12 @@ gr_status gr_workspace_offset(const gr_grid *grid, int kind, int stage, int fiel
  * prim_host: 5 cell arrays, E_host: 3 cell arrays, metric_host: 2 cell arrays
  * (alpha, psi) or NULL; all host arrays are compact (index i + Nx (j + Ny k),
  * stride Nx Ny Nz between fields) and are copied into the padded device
- * layout.  Also resets the failure counter and fills
- * the ghost points of the workspace stage storage.  With glm the face
- * fields are then turned into the cell-centred q_B^d (mean of the cell's two
- * d-faces; the face value itself along an inactive direction and at the last
- * point of the array) and q_Psi = q_Phi = 0 (Sec 3.1).  Synchronises the
- * stream. */
+ * layout.  Also resets the failure counter and sets every stage block of
+ * the workspace to a copy of the state, ghost points included.  With glm the
+ * face fields are then turned into the cell-centred q_B^d (mean of the
+ * cell's two d-faces; the face value itself along an inactive direction and
+ * at the last point of the array) and q_Psi = q_Phi = 0 (Sec 3.1).
+ * Synchronises the stream. */
 gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim_host, const double *E_host,
                         const double *A_host, const double *face_host, const double *metric_host,
                         hipStream_t stream);
@@ -155,11 +155,14 @@ gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim
  * update fused with the primitive recovery, Sec 2.4); pass p = s is the
  * final combination followed by the recovery with E and B known (Sec 2.6).
  * s = 2 for GR_SSP2_222, 4 for GR_SSP3_433.  Passes must run in order.
+ * No pass writes a ghost point: the boundary rules (outflow, periodic) are
+ * applied where a stencil reads beyond the interior, and ghost points of
+ * fixed boundaries keep the values they were initialised with.
  * In a pass that evaluates L on a grid of at least 2^20 interior cells, the
  * edge-EMF and face-update launches run on a second stream the library owns
  * (one per device, default priority, created by gr_init_state), forked from
- * `stream` with an event after the ghost fill and joined back before the cell
- * pass: the call stays ordered on `stream` and can be captured into a graph
+ * `stream` with an event at the start of the pass and joined back before the
+ * cell pass: the call stays ordered on `stream` and can be captured into a graph
  * from it.  Smaller grids launch everything on `stream`.  The second stream
  * is shared by every call on the device: forked calls from several host
  * threads queue their EMF launches on it one after another, and a call being

@@ -205,8 +205,7 @@ __global__ void __launch_bounds__(256) k_divb_partial(Geo G, FlatBox R, CPtr<3> 
 
 // GLM: central-difference divergence of the cell-centred q_B over the
 // interior, the boundary rule supplying the neighbour outside
-__global__ void __launch_bounds__(256) k_divb_cc_partial(Geo G, FlatBox R, BcArgs Bc, CPtr<3> qB,
-                                                         double *__restrict__ part)
+__global__ void __launch_bounds__(256) k_divb_cc_partial(Geo G, FlatBox R, CPtr<3> qB, double *__restrict__ part)
 {
     double a = 0.0, b = 0.0, c = 0.0;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < R.total; t += (long)gridDim.x * blockDim.x) {
@@ -217,7 +216,7 @@ __global__ void __launch_bounds__(256) k_divb_cc_partial(Geo G, FlatBox R, BcArg
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             if (!G.act[d]) continue;
-            int up = map_cell(G, Bc, d, p[d] + 1), dn = map_cell(G, Bc, d, p[d] - 1);
+            int up = stage_cell(G, d, p[d] + 1), dn = stage_cell(G, d, p[d] - 1);
             dv += (qB.p[d][id + (up - p[d]) * G.st[d]] - qB.p[d][id + (dn - p[d]) * G.st[d]]) * (0.5 * G.idx[d]);
         }
         a += fabs(dv);

@@ -14,6 +14,7 @@ struct Geo {
     int o;       // offset of point (0, 0, 0) from the start of its field
     long fs;     // field stride (doubles) of a field block
     double dx[3], idx[3];
+    int bc[3][2];  // boundary rule per direction and side (GR_OUTFLOW, ...)
 };
 
 template <int K>
@@ -225,61 +226,74 @@ __device__ __forceinline__ void recon_face(const double w[6], double &L, double 
     }
 }
 
-// window of one field along stride s around index id (face id between id-s and id)
-template <int REC>
-__device__ __forceinline__ void recon_at(const double *__restrict__ a, int id, int s, double &L, double &R)
-{
-    double w[6];
-    unsigned o = (unsigned)id << 3, sb = (unsigned)s << 3;
-    w[1] = ldb(a, o - 2 * sb);
-    w[2] = ldb(a, o - sb);
-    w[3] = ldb(a, o);
-    w[4] = ldb(a, o + sb);
-    if (REC == GR_PPM) {
-        w[0] = ldb(a, o - 3 * sb);
-        w[5] = ldb(a, o + 2 * sb);
-    } else {
-        w[0] = w[1];
-        w[5] = w[4];
-    }
-    recon_face<REC>(w, L, R);
-}
-
 // ---------------------------------------------------------------------------
 // boundary rules as index maps: the point whose value a ghost point takes
-// (outflow: the nearest interior point; periodic: the image; fixed: itself)
-struct BcArgs {
-    int bc[3][2];
-};
+// (outflow: the nearest interior point; periodic: the image; fixed: itself).  The stencil kernels read the stage fields (primitives, E,
+// face fields) through these maps, so no ghost point of a stage field is
+// ever written: a read at a ghost point goes to the point whose value the
+// rule gives it (fixed ghost points hold their initial values, set at
+// initialisation and never written).  Composing the maps of x, y and z gives
+// the values that filling the ghost points along x, then y, then z over the
+// full extent of the other directions would give.  The metric is static and
+// read at the point itself.
 
-__device__ __forceinline__ int map_cell(const Geo &G, const BcArgs &B, int d, int m)
+// index along d of the cell whose stage value cell m takes (m inside the
+// padded box; m itself inside the interior and along an inactive direction)
+__device__ __forceinline__ int stage_cell(const Geo &G, int d, int m)
 {
-    if (!G.act[d]) return m;
-    int g = G.g[d], n = G.n[d];
+    const int g = G.g[d], n = G.n[d];
     if (m < g) {
-        int b = B.bc[d][0];
+        const int b = G.bc[d][0];
         return b == GR_OUTFLOW ? g : (b == GR_PERIODIC ? m + n : m);
     }
     if (m >= g + n) {
-        int b = B.bc[d][1];
+        const int b = G.bc[d][1];
         return b == GR_OUTFLOW ? g + n - 1 : (b == GR_PERIODIC ? m - n : m);
     }
     return m;
 }
-// normal face field of direction d: faces g .. g+n are evolved
-__device__ __forceinline__ int map_face(const Geo &G, const BcArgs &B, int d, int m)
+// byte offset of the stage value of the neighbour delta = +-1 along d of an
+// interior cell c at byte offset o: the neighbour leaves the interior only
+// from the first (delta -1) or the last (+1) interior cell, where the rule
+// moves it by the same number of cells for every such cell
+__device__ __forceinline__ unsigned stage_nb(const Geo &G, const int c[3], unsigned o, int d, int delta)
 {
-    if (!G.act[d]) return m;
-    int g = G.g[d], n = G.n[d];
-    if (m < g) {
-        int b = B.bc[d][0];
-        return b == GR_OUTFLOW ? g : (b == GR_PERIODIC ? m + n : m);
+    const int g = G.g[d], n = G.n[d];
+    const int edge = delta > 0 ? g + n - 1 : g;  // the cell whose neighbour leaves
+    const int step = c[d] == edge ? stage_cell(G, d, edge + delta) - edge : delta;
+    return o + ((unsigned)(step * G.st[d]) << 3);
+}
+// reconstruction along d at the d-face below point c from the stage field a
+// (a cell field, or a face field whose normal is not d), the stencil points
+// mapped by the boundary rule along d (o: the byte offset of c, whose other
+// coordinates are already those of a stage value)
+template <int REC>
+__device__ __forceinline__ void recon_stage(const double *__restrict__ a, const Geo &G, const int c[3], unsigned o,
+                                            int d, double &L, double &R)
+{
+    const int m = c[d], g = G.g[d], n = G.n[d];
+    double w[6];
+    if (m - 3 >= g && m + 2 <= g + n - 1) {
+        const unsigned sb = (unsigned)G.st[d] << 3;
+        w[1] = ldb(a, o - 2 * sb);
+        w[2] = ldb(a, o - sb);
+        w[3] = ldb(a, o);
+        w[4] = ldb(a, o + sb);
+        if (REC == GR_PPM) {
+            w[0] = ldb(a, o - 3 * sb);
+            w[5] = ldb(a, o + 2 * sb);
+        }
+    } else {
+#pragma unroll
+        for (int k = (REC == GR_PPM ? 0 : 1); k < (REC == GR_PPM ? 6 : 5); k++) {
+            w[k] = ldb(a, o + ((unsigned)((stage_cell(G, d, m + k - 3) - m) * G.st[d]) << 3));
+        }
     }
-    if (m > g + n) {
-        int b = B.bc[d][1];
-        return b == GR_OUTFLOW ? g + n : (b == GR_PERIODIC ? m - n : m);
+    if (REC != GR_PPM) {
+        w[0] = w[1];
+        w[5] = w[4];
     }
-    return m;
+    recon_face<REC>(w, L, R);
 }
 
 }  // namespace gr

@@ -3,16 +3,17 @@
 // arXiv:2110.03732).
 //
 // Pass structure of one step (IMEX tableau with s implicit stages, Sec 2.3):
-//   pass p < s : [ghost fill + explicit operator L of stage p-1]
+//   pass p < s : [explicit operator L of stage p-1]
 //                -> stage faces -> cell accumulation q* -> fused implicit
 //                   E + velocity Newton solve (Sec 2.4)
 //   pass p = s : L of stage s-1 -> final combination -> recovery with E, B
 //                known (Sec 2.6)
 // The explicit operator (Sec 2.1 fluxes and sources, Sec 2.5 speeds, HLL,
-// Sec 3.2 upwind constrained transport): one ghost-fill launch, the x/y LDS
-// sweeps (reconstruction + HLL, flux divergence written), one EMF launch per
-// edge direction, the CT face update, and the cell pass that runs the z sweep
-// and the sources before the accumulation.  GLM cleaning (Sec 3.1) replaces
+// Sec 3.2 upwind constrained transport): the x/y LDS sweeps (reconstruction +
+// HLL, flux divergence written), one EMF launch per edge direction, the CT
+// face update, and the cell pass that runs the z sweep and the sources before
+// the accumulation.  The boundary rules enter as index maps in the stencil
+// reads (no ghost-fill launch).  GLM cleaning (Sec 3.1) replaces
 // the EMF and face-update launches by three more swept components.  A whole
 // step runs two consecutive point-wise passes as one cell launch where the
 // tableau allows (IMEX-SSP3: passes 0 and 1).  Device fields have rows padded
@@ -43,8 +44,8 @@ namespace {
 // measurement hook: launches of the selected kernel classes are bracketed by
 // HIP events on the stream they are launched on, with the algorithmic bytes
 // (every live input field read once, every output written once) of the launch
-enum KClass { KC_SWEEP = 0, KC_CT, KC_FACE_UPDATE, KC_CELL_UPDATE, KC_GHOST, KC_COUNT };
-const char *kClassNames[KC_COUNT] = {"k_xy", "k_ct", "k_face_update", "k_cell_update", "k_ghost_all"};
+enum KClass { KC_SWEEP = 0, KC_CT, KC_FACE_UPDATE, KC_CELL_UPDATE, KC_COUNT };
+const char *kClassNames[KC_COUNT] = {"k_xy", "k_ct", "k_face_update", "k_cell_update"};
 struct TRec {
     int cls;
     hipEvent_t a, b;
@@ -93,6 +94,8 @@ Geo make_geo(const gr_grid *g)
         G.N[d] = G.n[d] + 2 * G.g[d];
         G.dx[d] = G.act[d] ? (g->hi[d] - g->lo[d]) / g->n[d] : 1.0;
         G.idx[d] = 1.0 / G.dx[d];
+        G.bc[d][0] = g->bc[d][0];
+        G.bc[d][1] = g->bc[d][1];
     }
     // rows padded to whole 128-byte lines and the first interior point of
     // every row on a line boundary: a tile row of 16 cells is one line
@@ -528,8 +531,8 @@ void with_ct(int K, int F, Fn &&f)
     else byF(IC<2>{});
 }
 
-// Everything one pass of one run launches, in launch order: ghost fill,
-// x/y phases, the three EMF components, the face update, the cell pass.
+// Everything one pass of one run launches, in launch order: x/y phases, the
+// three EMF components, the face update, the cell pass.
 // a pass forks its EMF and face-update launches to the side stream only on
 // grids of at least this many cells: on smaller ones the two extra stream
 // dependencies cost more than the overlap gains (a 512^2 plane ran 8% slower
@@ -538,17 +541,16 @@ void with_ct(int K, int F, Fn &&f)
 constexpr long kForkCells = 1L << 20;
 
 struct PassPlan {
-    bool ghost = false, xy = false, face = false;
+    bool xy = false, face = false;
     bool fork = false;  // EMFs and face update beside the sweeps
     bool swz = false;  // cell pass with the z phase
     bool ct[3] = {false, false, false};
     int ctf[3] = {CT_BOX, CT_BOX, CT_BOX};  // EMF kernel form per launch
-    GhostArgs gh;
     XyArgs xya;
     CtArgs cta[3];
     FaceArgs fa;
     CellArgs ca;
-    double gh_bytes = 0, xy_bytes = 0, ct_bytes[3] = {0, 0, 0}, fa_bytes = 0, ca_bytes = 0;
+    double xy_bytes = 0, ct_bytes[3] = {0, 0, 0}, fa_bytes = 0, ca_bytes = 0;
 };
 
 GridDims flat_dims(const Region &R)
@@ -618,55 +620,6 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     const double ncell = (double)G.n[0] * G.n[1] * G.n[2];
 
     if (withL) {
-        // ghost points of the stage p-1 block
-        BcArgs B;
-        bool any = false;
-        for (int d = 0; d < 3; d++)
-            for (int e = 0; e < 2; e++) {
-                B.bc[d][e] = g->bc[d][e];
-                if (G.act[d] && g->bc[d][e] != GR_FIXED) any = true;
-            }
-        if (any) {
-            pl.ghost = true;
-            GhostArgs &a = pl.gh;
-            a.G = G;
-            a.B = B;
-            a.nslab = 0;
-            a.sb[0] = 0;
-            long shell = 0;
-            // slabs: z, then y inside the interior z, then x inside the interior y-z
-            for (int d = 2; d >= 0; d--) {
-                if (!G.act[d]) continue;
-                for (int side = 0; side < 2; side++) {
-                    Region R;
-                    for (int e = 0; e < 3; e++) {
-                        if (e > d) {  // already covered by the slabs of e: interior only
-                            R.lo[e] = G.g[e];
-                            R.cnt[e] = G.n[e];
-                        } else {
-                            R.lo[e] = 0;
-                            R.cnt[e] = G.N[e];
-                        }
-                    }
-                    R.lo[d] = side ? G.g[d] + G.n[d] : 0;
-                    R.cnt[d] = G.g[d];
-                    long pts = rtotal(R);
-                    if (pts == 0) continue;
-                    a.slab[a.nslab] = R;
-                    a.sb[a.nslab + 1] = a.sb[a.nslab] + (unsigned)((pts + kBlock - 1) / kBlock);
-                    a.nslab++;
-                    shell += pts;
-                }
-            }
-            a.ncells = Ly.nsp;
-            a.faces_cc = glm;
-            a.cells = ptrs<10>(sp_prev, G.fs);
-            if (!glm) a.cells.p[8] = a.cells.p[9] = nullptr;
-            a.faces = ptrs<3>(sf_prev, G.fs);
-            a.gd.x = a.sb[a.nslab];
-            a.gd.y = a.gd.z = 1;
-            pl.gh_bytes = 8.0 * shell * (Ly.nsp + 3) * 2;
-        }
         // x/y phases: reads 8 stage fields, 3 face fields, the metric; writes 8
         pl.xy = true;
         XyArgs &x = pl.xya;
@@ -730,11 +683,17 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
             f.Ls.Lst[d] = A.storeL ? wfield(st, G, Ly.L + 11 * (size_t)(p - 1) + 8 + d) : nullptr;
         }
         f.fout = ptrs<3>(fout, G.fs);
+        std::memset(&f.Eg, 0, sizeof(f.Eg));
+        if (withL)
+            for (int i = 0; i < 3; i++) f.Eg.p[i] = sp_prev + (size_t)(5 + i) * G.fs;
         f.gd = flat_dims(f.R);
         double nf = 0.0;
         for (int d = 0; d < 3; d++) nf += (double)rtotal(region(G, 1 << d));
         pl.fa_bytes = 8.0 * (nf * (1 + nLst + 1 + (int)A.storeL) + (withL ? 3.0 * rtotal(f.R) : 0.0));
     }
+    // the cell pass's charge reads the ghost layer of the stage E that the face
+    // update writes: every pass with L must have one (true of both tableaux)
+    if (withL && !glm && !pl.face) return GR_EUNSUPPORTED;
     // cells
     CellArgs &c = pl.ca;
     std::memset(&c, 0, sizeof(c));  // no paired stage unless run_pair sets one
@@ -870,15 +829,11 @@ gr_status side_stream(hipStream_t *out)
 
 gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
 {
-    if (pl.ghost) {
-        TScope ts(KC_GHOST, s, pl.gh_bytes);
-        hipLaunchKernelGGL(k_ghost_all, d3(pl.gh.gd), dim3(kBlock), 0, s, pl.gh);
-        LAUNCHCHK();
-    }
-    // The EMFs and the face update depend on the ghost fill only, the x/y
-    // sweeps too: with both present the EMFs and the face update go to the
-    // side stream (forked after the ghost fill) and the cell pass waits for
-    // them, so the memory-bound face update overlaps the sweeps.
+    // The EMFs and the face update depend only on the stage block of the
+    // previous pass, the x/y sweeps too: with both present the EMFs and the
+    // face update go to the side stream (forked at the start of the pass) and
+    // the cell pass waits for them, so the memory-bound face update overlaps
+    // the sweeps.
     bool ct_any = pl.face;
     for (int i = 0; i < 3; i++) ct_any |= pl.ct[i] != 0;
     hipStream_t s2 = s;
@@ -1101,19 +1056,6 @@ gr_status build_launches(gr_batch *b, int p_only, unsigned cls_mask, const std::
                 }
             }
         }
-        // ghost fill
-        if (cls_mask & (1u << KC_GHOST)) {
-            std::vector<const GhostArgs *> a;
-            std::vector<double> by;
-            for (int r = 0; r < nr; r++)
-                if (use[r] && pl[r].ghost) {
-                    a.push_back(&pl[r].gh);
-                    by.push_back(pl[r].gh_bytes);
-                }
-            BLaunch L;
-            L.cls = KC_GHOST;
-            add_group(stg, out, L, a, by);
-        }
         // x/y phases, grouped by (recon, metric, tile)
         if (cls_mask & (1u << KC_SWEEP)) {
             for (int rec = 0; rec < 3; rec++)
@@ -1271,9 +1213,6 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
     if (L.total == 0) return GR_OK;
     const dim3 grid(L.total);
     switch (L.cls) {
-    case KC_GHOST:
-        hipLaunchKernelGGL(kb_ghost_all, grid, dim3(kBlock), 0, s, (const GhostArgs *)L.args, L.start, L.n);
-        break;
     case KC_SWEEP:
         with_rm(L.V.rec, L.V.met, [&](auto R, auto M) {
             with_flag(L.V.glm, [&](auto GL) {
@@ -1337,11 +1276,12 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
     return GR_OK;
 }
 
-// The list holds, per pass, ghost fills, then x/y sweeps, EMFs and the face
-// update (which all depend on the ghost fill only), then the cell launches.
+// The list holds, per pass, x/y sweeps, EMFs and the face update (which all
+// depend only on the stage block of the previous pass), then the cell
+// launches.
 // With a side stream (a batch of at least kForkCells cells), as in the plain
 // path, where a pass has both sweeps and EMF / face-update launches, the
-// latter go to the side stream, forked after the ghost fill, and the cell
+// latter go to the side stream, forked at the start of the pass, and the cell
 // launches wait for them.  side == nullptr: everything on s.
 gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, hipStream_t side)
 {
@@ -1649,10 +1589,7 @@ gr_status divb_norm_into(const gr_grid *g, const gr_state *st, double *part, dou
     FlatBox B = flatbox(G);
     unsigned nb = nblocks(B.total);
     if (g->glm) {
-        BcArgs Bc;
-        for (int d = 0; d < 3; d++)
-            for (int e = 0; e < 2; e++) Bc.bc[d][e] = g->bc[d][e];
-        hipLaunchKernelGGL(k_divb_cc_partial, dim3(nb), dim3(256), 0, s, G, B, Bc, cptrs<3>(st->face, G.fs), part);
+        hipLaunchKernelGGL(k_divb_cc_partial, dim3(nb), dim3(256), 0, s, G, B, cptrs<3>(st->face, G.fs), part);
     } else {
         hipLaunchKernelGGL(k_divb_partial, dim3(nb), dim3(256), 0, s, G, B, cptrs<3>(st->face, G.fs), part);
     }
@@ -1872,7 +1809,8 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
         HIPCHK(hipMemsetAsync(st->q + 8 * G.fs, 0, 2 * G.fs * sizeof(double), s));
     }
     // every stage block starts as a copy of the state (ghost points of fixed
-    // boundaries keep these values)
+    // boundaries keep these values: no kernel writes a ghost point of a stage
+    // field)
     for (int j = 0; j < T.s; j++) {
         double *spj = wfield(st, G, Ly.sprim + (size_t)Ly.nsp * j);
         hipLaunchKernelGGL(k_stage_copy, gr, bl, 0, s, G, g->metric, cptrs<5>(st->prim, G.fs), cptrs<8>(st->q, G.fs),

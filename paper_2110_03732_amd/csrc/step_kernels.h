@@ -1,7 +1,5 @@
 // step_kernels.h -- gfx950 kernels of one explicit-operator + implicit pass.
 //
-//   k_ghost_all   one launch over the padded box: outflow / periodic / fixed
-//                 ghost points of the stage primitives, E and face fields
 //   k_xy          x and y phases of the explicit operator on an LDS-staged
 //                 tile: reconstruction of the ten face variables, HLL flux
 //                 on every face, flux divergence
@@ -23,85 +21,9 @@ namespace gr {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
-// ghost points: the per-direction index maps map_cell / map_face (common.h)
-// composed over x, y, z equal filling x, then y, then z over the full extent
-// of the other directions
-
-// the ghost shell as up to six slabs (z low/high over the whole x-y extent,
-// y low/high inside the interior z range, x low/high inside the interior
-// y-z range); sb[i] is the first block of slab i, one thread per point
-struct GhostArgs {
-    Geo G;
-    BcArgs B;
-    Region slab[6];
-    unsigned sb[7];
-    int nslab;
-    int ncells;    // 8, or 10 with GLM (Psi, Phi)
-    int faces_cc;  // GLM: the three "face" fields are cell centred
-    Ptr<10> cells;
-    Ptr<3> faces;
-    GridDims gd;
-};
-__device__ __forceinline__ void ghost_body(const GhostArgs &a, Blk blk)
-{
-    const Geo &G = a.G;
-    const BcArgs &B = a.B;
-    const Ptr<10> &cells = a.cells;
-    const Ptr<3> &faces = a.faces;
-    const unsigned L = blk.x;
-    int k = 0;
-    while (k + 1 < a.nslab && L >= a.sb[k + 1]) k++;
-    const Region &R = a.slab[k];
-    const long t = (long)(L - a.sb[k]) * blockDim.x + threadIdx.x;
-    const long cnt01 = (long)R.cnt[0] * R.cnt[1];
-    if (t >= cnt01 * R.cnt[2]) return;
-    int c[3];
-    c[2] = R.lo[2] + (int)(t / cnt01);
-    const long r = t - (long)(c[2] - R.lo[2]) * cnt01;
-    c[1] = R.lo[1] + (int)(r / R.cnt[0]);
-    c[0] = R.lo[0] + (int)(r - (long)(c[1] - R.lo[1]) * R.cnt[0]);
-    int s[3];
-    bool move = false;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        s[d] = map_cell(G, B, d, c[d]);
-        move |= (s[d] != c[d]);
-    }
-    unsigned o = (unsigned)lin(G, c) << 3;
-    if (move) {
-        unsigned os = (unsigned)lin(G, s) << 3;
-#pragma unroll
-        for (int v = 0; v < 8; v++) stb(cells.p[v], o, ldb(cells.p[v], os));
-        if (a.ncells > 8) {
-            stb(cells.p[8], o, ldb(cells.p[8], os));
-            stb(cells.p[9], o, ldb(cells.p[9], os));
-        }
-        if (a.faces_cc) {
-#pragma unroll
-            for (int f = 0; f < 3; f++) stb(faces.p[f], o, ldb(faces.p[f], os));
-        }
-    }
-    if (a.faces_cc) return;
-#pragma unroll
-    for (int f = 0; f < 3; f++) {
-        int sf[3];
-        bool mv = false;
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            sf[d] = (d == f) ? map_face(G, B, d, c[d]) : s[d];
-            mv |= (sf[d] != c[d]);
-        }
-        if (mv) stb(faces.p[f], o, ldb(faces.p[f], (unsigned)lin(G, sf) << 3));
-    }
-}
-__global__ void __launch_bounds__(kBlock) k_ghost_all(GhostArgs a) { ghost_body(a, blk_of(hw_linear<false>(), a.gd)); }
-__global__ void __launch_bounds__(kBlock)
-    kb_ghost_all(const GhostArgs *__restrict__ aa, const unsigned *__restrict__ start, int n)
-{
-    unsigned lb;
-    const GhostArgs &a = aa[batch_locate<false>(start, n, lb)];
-    ghost_body(a, blk_of(lb, a.gd));
-}
+// No kernel writes a ghost point of a stage field: every read of a stage
+// field at a point beyond the interior goes where the boundary rule puts it
+// (stage_cell, common.h).
 
 // ---------------------------------------------------------------------------
 // HLL flux at one face of direction D from the reconstructed states of the
@@ -164,9 +86,11 @@ __device__ __forceinline__ void hll_face(const Phys &P, const double *sL, const 
 // read the cell's own value and 0.5 (b + b) = b exactly, so the loads of a
 // staging round never wait behind a branch.
 template <int MET, bool GLM = false>
-__device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const CPtr<2> &met, const int c[3], int t)
+__device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const CPtr<2> &met, const int c[3],
+                                        unsigned o, unsigned om, int t)
 {
-    unsigned o = (unsigned)lin(G, c) << 3;
+    // face values at byte offset o (the point whose stage values point c
+    // takes; the same as c along t), the metric at om (c itself)
     double b;
     if constexpr (!GLM) {
         const bool act = G.act[t];
@@ -178,7 +102,7 @@ __device__ __forceinline__ double bcc_t(const Geo &G, const CPtr<3> &sf, const C
         b = ldb(sf.p[t], o);
     }
     if (MET) {
-        double ps = ldb(met.p[1], o);
+        double ps = ldb(met.p[1], om);
         double p2 = ps * ps;
         b *= frcp(p2 * p2 * p2);
     }
@@ -239,7 +163,10 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
 
     // every load of the staging rounds is issued, unconditionally, before the
     // first LDS store (lanes past the end of the last round load its last
-    // point again and store nothing)
+    // point again and store nothing); only a tile whose halo reaches beyond
+    // the interior along D maps its points by the boundary rule (the test is
+    // the same for the whole block)
+    const bool bmap = org[D] - H < G.g[D] || org[D] + (D == 0 ? T0 : (D == 1 ? T1 : T2)) + H > G.g[D] + G.n[D];
     constexpr int NR = (NRAW + NT - 1) / NT;
     double st[NR][NV];
 #pragma unroll
@@ -251,13 +178,16 @@ __device__ __forceinline__ void sweep_phase(const Geo &G, const Phys &P, const C
             c[D] -= H;
 #pragma unroll
             for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
-            unsigned o = (unsigned)lin(G, c) << 3;
+            // the stage values of a point beyond the interior along D are
+            // those the boundary rule gives it
+            const unsigned om = (unsigned)lin(G, c) << 3;
+            const unsigned o = bmap ? om + ((unsigned)((stage_cell(G, D, c[D]) - c[D]) * G.st[D]) << 3) : om;
 #pragma unroll
             for (int v = 0; v < 8; v++) st[k][v] = ldb(sp.p[v], o);
-            st[k][8] = bcc_t<MET, GLM>(G, sf, met, c, t1);
-            st[k][9] = bcc_t<MET, GLM>(G, sf, met, c, t2);
+            st[k][8] = bcc_t<MET, GLM>(G, sf, met, c, o, om, t1);
+            st[k][9] = bcc_t<MET, GLM>(G, sf, met, c, o, om, t2);
             if (GLM) {
-                st[k][10] = bcc_t<MET, GLM>(G, sf, met, c, D);
+                st[k][10] = bcc_t<MET, GLM>(G, sf, met, c, o, om, D);
                 st[k][11] = ldb(sp.p[8], o);
                 st[k][12] = ldb(sp.p[9], o);
             }
@@ -510,19 +440,24 @@ struct CtArgs {
 // inactive d), weighted by the face speeds; these are equal (metric-only), so
 // the weighted velocity is the mean of the two
 template <int REC, int MET, int D, int J>
-__device__ __forceinline__ double ct_vbar(const Geo &G, const CtArgs &a, int id)
+__device__ __forceinline__ double ct_vbar(const Geo &G, const CtArgs &a, const int c[3])
 {
-    const unsigned o = (unsigned)id << 3;
+    const unsigned o = (unsigned)lin(G, c) << 3;
     double al, ps;
     face_metric<MET>(G, a.met, o, D, al, ps);
     const double p2 = ps * ps;
+    // the stage u~ where the boundary rule puts the points (the row mapped
+    // across D, the stencil along D point by point)
+    int cm[3] = {stage_cell(G, 0, c[0]), stage_cell(G, 1, c[1]), stage_cell(G, 2, c[2])};
+    cm[D] = c[D];
+    const unsigned om = (unsigned)lin(G, cm) << 3;
     double uL[3], uR[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         if (G.act[D]) {
-            recon_at<REC>(a.u.p[i], id, G.st[D], uL[i], uR[i]);
+            recon_stage<REC>(a.u.p[i], G, cm, om, D, uL[i], uR[i]);
         } else {
-            uL[i] = uR[i] = ldb(a.u.p[i], o);
+            uL[i] = uR[i] = ldb(a.u.p[i], om);
         }
     }
     // W^2 = 1 + psi^4 |u~|^2 (orthonormal u = psi^2 u~)
@@ -577,15 +512,18 @@ __device__ __forceinline__ void ct_ideal_body(const CtArgs &args, Blk blk)
         const int e[3] = {l % E0, (l / E0) % E1, l / (E0 * E1)};
         int c[3];
         clamp_pos(e, B, c);
-        const int id = lin(G, c);
-        sVb[l] = ct_vbar<REC, MET, A, B>(G, args, id);
-        sQa[l] = ldb(sf.p[A], (unsigned)id << 3);
+        sVb[l] = ct_vbar<REC, MET, A, B>(G, args, c);
+        // q_B^a of the row where the boundary rule puts it (the a-face itself
+        // stays inside the evolved range)
+        int cq[3] = {c[0], c[1], c[2]};
+        cq[B] = stage_cell(G, B, c[B]);
+        sQa[l] = ldb(sf.p[A], (unsigned)lin(G, cq) << 3);
     }
     for (int l = tid; l < NLA; l += kBlock) {
         const int e[3] = {l % F0, (l / F0) % F1, l / (F0 * F1)};
         int c[3];
         clamp_pos(e, A, c);
-        sVa[l] = ct_vbar<REC, MET, B, A>(G, args, lin(G, c));
+        sVa[l] = ct_vbar<REC, MET, B, A>(G, args, c);
     }
     __syncthreads();
 
@@ -615,10 +553,11 @@ __device__ __forceinline__ void ct_ideal_body(const CtArgs &args, Blk blk)
     } else {
         vaL = vaR = sVa[r1];
     }
-    const int id = lin(G, c);
-    const unsigned o = (unsigned)id << 3;
+    const unsigned o = (unsigned)lin(G, c) << 3;
+    // q_B^b along A around the edge, the stencil points where the boundary
+    // rule puts them (the edge lies inside the evolved range along B and K)
     if (actA) {
-        recon_at<REC>(sf.p[B], id, G.st[A], qbL, qbR);
+        recon_stage<REC>(sf.p[B], G, c, o, A, qbL, qbR);
     } else {
         qbL = qbR = ldb(sf.p[B], o);
     }
@@ -669,7 +608,12 @@ __device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
 
     // ---- step 1: a-face states of psi^4 E_k and q_B^a, clamped into range;
     // a lane's loads of all its rounds are issued before the first use (lanes
-    // past the end of the last round repeat its last point and store nothing)
+    // past the end of the last round repeat its last point and store nothing).
+    // Only a block whose rows (widened by HB along b) or E stencils (3 along a)
+    // leave the interior maps its points by the boundary rule.
+    constexpr int TA_ = CtTileF<K, F>::T[A], TB_ = CtTileF<K, F>::T[B];
+    const bool bmap = (actA && (org[A] - 3 < G.g[A] || org[A] + TA_ + 2 > G.g[A] + G.n[A] - 1)) ||
+                      (actB && (org[B] - HB < G.g[B] || org[B] + TB_ + HB > G.g[B] + G.n[B]));
     constexpr int NR = (NL + kBlock - 1) / kBlock;
     double wE[NR][6], wP[NR][2], wQ[NR];
 #pragma unroll
@@ -690,21 +634,31 @@ __device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
             c[d] = c[d] < lo ? lo : (c[d] > hi ? hi : c[d]);
         }
         const unsigned o = (unsigned)lin(G, c) << 3, sa = (unsigned)G.st[A] << 3;
+        // stage values where the boundary rule puts the point: the row mapped
+        // along B (the a-face of q_B^a and the stencil centre stay inside the
+        // evolved range along A), each E_K stencil point along A by itself;
+        // the metric at the point itself
+        int cm[3] = {c[0], c[1], c[2]};
+        if (bmap) cm[B] = stage_cell(G, B, c[B]);
+        const unsigned om = (unsigned)lin(G, cm) << 3;
         if (actA) {
+            const int m0 = c[A];
+            const bool in = !bmap || (m0 - 3 >= G.g[A] && m0 + 2 <= G.g[A] + G.n[A] - 1);
 #pragma unroll
             for (int m = 0; m < 6; m++) {
                 // minmod and MC use the four middle points (the outer two are copies)
                 const int mm = REC == GR_PPM ? m : (m == 0 ? 1 : (m == 5 ? 4 : m));
-                wE[r][m] = ldb(Ek, o + (unsigned)(mm - 3) * sa);
+                const int dm = in ? mm - 3 : stage_cell(G, A, m0 + mm - 3) - m0;
+                wE[r][m] = ldb(Ek, om + ((unsigned)(dm * G.st[A]) << 3));
             }
         } else {
-            wE[r][0] = ldb(Ek, o);
+            wE[r][0] = ldb(Ek, om);
         }
         if (MET) {
             wP[r][1] = ldb(met.p[1], o);
             wP[r][0] = actA ? ldb(met.p[1], o - sa) : wP[r][1];
         }
-        wQ[r] = ldb(sf.p[A], o);
+        wQ[r] = ldb(sf.p[A], om);
     }
 #pragma unroll
     for (int r = 0; r < NR; r++) {
@@ -750,10 +704,11 @@ __device__ __forceinline__ void ct_body_direct(const CtArgs &args, Blk blk)
         ERL = ERR = sER[r0];
         qaL = qaR = sQa[r0];
     }
-    const int id = lin(G, c);
-    const unsigned o = (unsigned)id << 3;
+    const unsigned o = (unsigned)lin(G, c) << 3;
+    // q_B^b along A around the edge, the stencil points where the boundary
+    // rule puts them (the edge lies inside the evolved range along B and K)
     if (actA) {
-        recon_at<REC>(sf.p[B], id, G.st[A], qbL, qbR);
+        recon_stage<REC>(sf.p[B], G, c, o, A, qbL, qbR);
     } else {
         qbL = qbR = ldb(sf.p[B], o);
     }
@@ -810,18 +765,25 @@ struct CtBox {
 // halves: ct_load issues a lane's loads unconditionally (lanes past the box
 // end load its last point again), ct_store writes them to LDS.  A kernel
 // issues the loads of all its boxes before the first store, so a wave keeps
-// every load in flight at once.
+// every load in flight at once.  MAP: the directions (bit d) along which the
+// box is widened beyond the tile, where a stage field is read at the point
+// the boundary rule gives (the other directions stay inside the evolved
+// range; 0 for the metric, read at the point itself).
 template <class BX>
 struct CtRegs {
     static constexpr int NR = (BX::N + kBlock - 1) / kBlock;
     double v[NR];
 };
-template <class BX>
+template <class BX, int MAP>
 __device__ __forceinline__ void ct_load(const Geo &G, const double *__restrict__ f, const int org[3], CtRegs<BX> &R)
 {
     constexpr int NR = CtRegs<BX>::NR;
     constexpr unsigned X0 = BX::X[0], X1 = BX::X[1];
     const int b[3] = {org[0] + BX::O[0], org[1] + BX::O[1], org[2] + BX::O[2]};
+    bool bmap = false;  // the same for the whole block
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+        if (MAP & (1 << d)) bmap |= b[d] < G.g[d] || b[d] + BX::X[d] > G.g[d] + G.n[d];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         unsigned l = threadIdx.x + (unsigned)(r * kBlock);
@@ -829,7 +791,10 @@ __device__ __forceinline__ void ct_load(const Geo &G, const double *__restrict__
         const unsigned e0 = l % X0, q = l / X0, e1 = q % X1, e2 = q / X1;
         int c[3] = {b[0] + (int)e0, b[1] + (int)e1, b[2] + (int)e2};
 #pragma unroll
-        for (int d = 0; d < 3; d++) c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
+        for (int d = 0; d < 3; d++) {
+            c[d] = c[d] < 0 ? 0 : (c[d] > G.N[d] - 1 ? G.N[d] - 1 : c[d]);
+            if ((MAP & (1 << d)) && bmap) c[d] = stage_cell(G, d, c[d]);
+        }
         R.v[r] = ldb(f, (unsigned)lin(G, c) << 3);
     }
 }
@@ -875,12 +840,12 @@ __device__ __forceinline__ void ct_body(const CtArgs &args, Blk blk)
         CtRegs<BQb> rQb;
         CtRegs<BP> rP;
         CtRegs<BA> rA;
-        ct_load<BE>(G, args.Ek, org, rE);
-        ct_load<BQa>(G, args.sf.p[A], org, rQa);
-        ct_load<BQb>(G, args.sf.p[B], org, rQb);
+        ct_load<BE, (1 << A) | (1 << B)>(G, args.Ek, org, rE);
+        ct_load<BQa, 1 << B>(G, args.sf.p[A], org, rQa);
+        ct_load<BQb, 1 << A>(G, args.sf.p[B], org, rQb);
         if (MET) {
-            ct_load<BP>(G, args.met.p[1], org, rP);
-            ct_load<BA>(G, args.met.p[0], org, rA);
+            ct_load<BP, 0>(G, args.met.p[1], org, rP);
+            ct_load<BA, 0>(G, args.met.p[0], org, rA);
         }
         ct_store<BE>(rE, sE);
         ct_store<BQa>(rQa, sQa);
@@ -1048,6 +1013,9 @@ struct FaceArgs {
     CPtr<3> EM, fn;
     FaceLs Ls;
     Ptr<3> fout;
+    // passes with L: the stage E read by this pass, whose ghost layer next to
+    // the interior this launch writes (null otherwise)
+    Ptr<3> Eg;
     GridDims gd;
 };
 __device__ __forceinline__ void face_body(const FaceArgs &a, Blk blk)
@@ -1085,6 +1053,29 @@ __device__ __forceinline__ void face_body(const FaceArgs &a, Blk blk)
         }
         if (A.storeL) stb(Ls.Lst[d], o, A.foldL ? fold + A.fL[A.p - 1] * Lnew : Lnew);
         stb(fout.p[d], o, acc);
+    }
+    // The cell pass forms the Gauss-law charge from the stage E of the
+    // neighbours of each interior cell, the only reads of a stage field at a
+    // ghost point that do not go through the boundary maps (they would keep
+    // the cell pass's coordinates in registers through its Newton solve).
+    // This launch runs before that cell pass and beside kernels that never
+    // read these points: the ghost cell next to the interior along d takes
+    // the value the boundary rule gives it (outflow, periodic; a fixed ghost
+    // point keeps its value).
+    if (a.Eg.p[0]) {
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const int m1 = (d + 1) % 3, m2 = (d + 2) % 3;
+            if (!G.act[d] || !in[m1] || !in[m2]) continue;
+            const int gp = c[d] == G.g[d] ? G.g[d] - 1 : (c[d] == G.g[d] + G.n[d] ? c[d] : -1);
+            if (gp < 0) continue;
+            const int src = stage_cell(G, d, gp);
+            if (src == gp) continue;
+            const unsigned og = o + ((unsigned)((gp - c[d]) * G.st[d]) << 3);
+            const unsigned os = o + ((unsigned)((src - c[d]) * G.st[d]) << 3);
+#pragma unroll
+            for (int i = 0; i < 3; i++) stb(a.Eg.p[i], og, ldb(a.Eg.p[i], os));
+        }
     }
 }
 __global__ void __launch_bounds__(kBlock) k_face_update(FaceArgs a) { face_body(a, blk_of(hw_linear<false>(), a.gd)); }
@@ -1207,7 +1198,12 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
         for (int d = 0; d < 3; d++) {
             if (!act(d)) continue;
             unsigned sd = (unsigned)G.st[d] << 3;
-            double qp = ldb(io.spm[5 + d], o + sd), qm = ldb(io.spm[5 + d], o - sd);
+            // stage E of the neighbours: the ghost layer next to the interior
+            // holds the boundary rule's values (written by this pass's face
+            // update; GLM, which has none, maps the neighbours); the metric
+            // at the neighbours themselves
+            const unsigned op = GLM ? stage_nb(G, c, o, d, 1) : o + sd, om = GLM ? stage_nb(G, c, o, d, -1) : o - sd;
+            double qp = ldb(io.spm[5 + d], op), qm = ldb(io.spm[5 + d], om);
             if (MET) {
                 double a = ldb(io.met[1], o + sd), b = ldb(io.met[1], o - sd);
                 double a2 = a * a, b2 = b * b;
@@ -1228,9 +1224,9 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
 #pragma unroll
             for (int d = 0; d < 3; d++) {
                 if (!act(d)) continue;
-                unsigned sd = (unsigned)G.st[d] << 3;
-                double dPsi = (ldb(io.spm[8], o + sd) - ldb(io.spm[8], o - sd)) * (0.5 * G.idx[d]);
-                double dPhi = (ldb(io.spm[9], o + sd) - ldb(io.spm[9], o - sd)) * (0.5 * G.idx[d]);
+                const unsigned op = stage_nb(G, c, o, d, 1), om = stage_nb(G, c, o, d, -1);
+                double dPsi = (ldb(io.spm[8], op) - ldb(io.spm[8], om)) * (0.5 * G.idx[d]);
+                double dPhi = (ldb(io.spm[9], op) - ldb(io.spm[9], om)) * (0.5 * G.idx[d]);
                 Lc[5 + d] -= al * ps2 * dPsi;
                 Lc[8 + d] -= al * ps2 * dPhi;
             }
@@ -1534,7 +1530,7 @@ __device__ __forceinline__ void cell_body(const CellArgs &args, Blk blk)
     if (status == 2) atomicAdd(io.nfail, 1ull);
 }
 template <int REC, int MET, int SWZ, int TX, int TZ, bool XI, bool GLM, bool PAIR = false>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PAIR && !XI ? 3 : 1)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((SWZ || PAIR) && !XI && !GLM ? 3 : 1)))
     k_cell_update(CellArgs a)
 {
     cell_body<REC, MET, SWZ, TX, TZ, XI, GLM, PAIR>(a, blk_of(hw_linear<SWZ != 0>(), a.gd));

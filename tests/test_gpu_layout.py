@@ -122,19 +122,19 @@ def test_whole_step_equals_stage_by_stage(name):
 
 def test_batch_step_pairs_the_point_wise_passes():
     """one step of a batch holding one IMEX-SSP3 star: pass 0 (with pass 1
-    inside it) launches the cell pass only, passes 2-4 launch ghost fill, x/y
-    sweeps, three EMF directions, face update and cell pass: 22 launches (23
-    with the passes run one by one); a GLM run is never paired"""
+    inside it) launches the cell pass only, passes 2-4 launch the x/y sweeps,
+    three EMF directions, face update and cell pass: 19 launches (20 with the
+    passes run one by one); a GLM run is never paired"""
     _torch()
     from paper_2110_03732_amd import grmhd
     s = W.tov_star(16)
     run = grmhd.Run(s, device="cuda:0")
     b = grmhd.Batch([run], [run.dt()])
-    assert b.stats()[0] == 22
+    assert b.stats()[0] == 19
     b.close()
     g = W.glm_monopole(16, kappa=1.0, ndim=3, imex=W.SSP3)
     rg = grmhd.Run(g, device="cuda:0")
     bg = grmhd.Batch([rg], [rg.dt()])
     # GLM: no EMF and face launches; passes 0 and 1 one by one
-    assert bg.stats()[0] == 1 + 1 + 3 * 3
+    assert bg.stats()[0] == 1 + 1 + 3 * 2
     bg.close()
