@@ -138,3 +138,93 @@ def test_batch_step_pairs_the_point_wise_passes():
     # GLM: no EMF and face launches; passes 0 and 1 one by one
     assert bg.stats()[0] == 1 + 1 + 3 * 2
     bg.close()
+
+
+GHOST_CASES = {
+    "blast_2d_37_outflow_mc": lambda: W.blast_wave(37, eta=1e-2, recon=W.MC, imex=W.SSP2),
+    "loop_2d_40x20_periodic": lambda: W.loop_advection(40, 20),
+    "star_3d_20_outflow": lambda: W.tov_star(20),
+    "star_3d_17_uct_ideal": lambda: _with(W.tov_star(17), uct=1),
+    "shock_tube_1d_101_ppm_ssp3": lambda: W.shock_tube(101, recon=W.PPM, imex=W.SSP3),
+    "glm_monopole_2d_33": lambda: W.glm_monopole(33, kappa=5.0, ndim=2),
+    "dynamo_1d_periodic": lambda: W.steady_dynamo(64, k=1),
+}
+
+
+def _ghost_mask(run, face_dir=None):
+    """True on the ghost points of one device field (points of the padded box
+    outside the interior; for the face field of normal face_dir the
+    boundary faces g + n along it are evolved, not ghosts)"""
+    s = run.setup
+    Nz, Ny, Nx = s.shape
+    g = s.ng
+    lo, hi = [0, 0, 0], [Nx, Ny, Nz]
+    for d in range(3):
+        if s.active(d):
+            n = (Nx, Ny, Nz)[d] - 2 * g
+            lo[d], hi[d] = g, g + n + (1 if d == face_dir else 0)
+    m = np.zeros(run.fs, dtype=bool)
+    z, y, x = np.meshgrid(np.arange(Nz), np.arange(Ny), np.arange(Nx), indexing="ij")
+    ghost = ~((x >= lo[0]) & (x < hi[0]) & (y >= lo[1]) & (y < hi[1]) & (z >= lo[2]) & (z < hi[2]))
+    idx = run.origin + x + run.pitch * (y + Ny * z)
+    m[idx[ghost]] = True
+    return m
+
+
+@pytest.mark.parametrize("name", sorted(GHOST_CASES))
+def test_ghost_points_never_read_or_written(name):
+    """outflow and periodic grids: every ghost point of the state (q, faces,
+    primitives) and of the workspace stage blocks set to NaN after
+    initialisation; three steps and the cleaning give the clean run's results
+    bit for bit (no kernel reads a ghost point of a stage field: the
+    boundary maps give every such read its interior point; the one ghost
+    layer of the stage E the cell pass reads is written in the pass before
+    it is read), and the state's ghost points are still NaN"""
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd
+    print("ghost case %s" % name, flush=True)
+    s = GHOST_CASES[name]()
+    assert all(b != W.FIXED for side in s.bc for b in side)
+    clean = grmhd.Run(s, device="cuda:0")
+    dirty = grmhd.Run(s, device="cuda:0")
+    dev = dirty.q.device
+    cell = torch.from_numpy(_ghost_mask(dirty)).to(dev)
+    face = [torch.from_numpy(_ghost_mask(dirty, None if s.glm else d)).to(dev) for d in range(3)]
+    torch.cuda.synchronize()
+    state = [(dirty.q.view(dirty.nq, dirty.fs), [cell] * dirty.nq), (dirty.prim.view(5, dirty.fs), [cell] * 5),
+             (dirty.face.view(3, dirty.fs), face)]
+    for t, masks in state:
+        for f, m in enumerate(masks):
+            t[f][m] = float("nan")
+    nstage = 4 if s.imex == W.SSP3 else 2
+    for j in range(nstage):
+        for f in range(10 if s.glm else 8):
+            off = grmhd.gr_workspace_offset(dirty.grid, 0, j, f) // 8
+            dirty.work[off: off + dirty.fs][cell] = float("nan")
+        for d in range(3):
+            off = grmhd.gr_workspace_offset(dirty.grid, 1, j, d) // 8
+            dirty.work[off: off + dirty.fs][face[d]] = float("nan")
+    torch.cuda.synchronize()
+    dt = clean.dt()
+    assert dirty.dt() == dt
+    for _ in range(3):
+        clean.step(dt)
+        dirty.step(dt)
+    if not s.glm:
+        assert np.array_equal(clean.clean_divB(2)[1], dirty.clean_divB(2)[1])
+    assert np.array_equal(clean.divB(), dirty.divB())
+    assert clean.fail_count() == dirty.fail_count()
+    sl = s.interior
+    for a, b in ((clean.prims(), dirty.prims()), (clean.cons(), dirty.cons())):
+        assert np.array_equal(a[(slice(None),) + sl], b[(slice(None),) + sl])
+    # faces compared on the device layout: every evolved face
+    torch.cuda.synchronize()
+    for d in range(3):
+        keep = ~face[d].cpu().numpy() & ~_pad_mask(dirty)
+        a = clean.face.view(3, clean.fs)[d].cpu().numpy()[keep]
+        b = dirty.face.view(3, dirty.fs)[d].cpu().numpy()[keep]
+        assert np.array_equal(a, b), d
+        assert np.all(np.isnan(dirty.face.view(3, dirty.fs)[d].cpu().numpy()[face[d].cpu().numpy()])), "ghost face written"
+    for t, nf in ((dirty.q, dirty.nq), (dirty.prim, 5)):
+        g = t.view(nf, dirty.fs)[:, cell].cpu().numpy()
+        assert np.all(np.isnan(g)), "ghost point of the state written"
