@@ -155,9 +155,11 @@ gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim
  * update fused with the primitive recovery, Sec 2.4); pass p = s is the
  * final combination followed by the recovery with E and B known (Sec 2.6).
  * s = 2 for GR_SSP2_222, 4 for GR_SSP3_433.  Passes must run in order.
- * No pass writes a ghost point: the boundary rules (outflow, periodic) are
- * applied where a stencil reads beyond the interior, and ghost points of
- * fixed boundaries keep the values they were initialised with.
+ * No pass writes a ghost point of the state: the boundary rules (outflow,
+ * periodic) are applied where a stencil reads beyond the interior, and ghost
+ * points of fixed boundaries keep the values they were initialised with (in
+ * the workspace, a pass with L writes the layer of stage E next to the
+ * interior, which its cell pass reads for the Gauss-law charge).
  * In a pass that evaluates L on a grid of at least 2^20 interior cells, the
  * edge-EMF and face-update launches run on a second stream the library owns
  * (one per device, default priority, created by gr_init_state), forked from
