@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define GR_ABI_VERSION 5
+#define GR_ABI_VERSION 6
 
 typedef enum {
     GR_OK = 0,

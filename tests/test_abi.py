@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     L = grmhd.lib()
     for name in declared_symbols():
         assert hasattr(L, name), name
-    assert grmhd.gr_abi_version() == 5
+    assert grmhd.gr_abi_version() == 6
 
 
 def test_validation_rejects_bad_grids():
