@@ -228,14 +228,16 @@ __device__ __forceinline__ void recon_face(const double w[6], double &L, double 
 
 // ---------------------------------------------------------------------------
 // boundary rules as index maps: the point whose value a ghost point takes
-// (outflow: the nearest interior point; periodic: the image; fixed: itself).  The stencil kernels read the stage fields (primitives, E,
-// face fields) through these maps, so no ghost point of a stage field is
-// ever written: a read at a ghost point goes to the point whose value the
-// rule gives it (fixed ghost points hold their initial values, set at
-// initialisation and never written).  Composing the maps of x, y and z gives
-// the values that filling the ghost points along x, then y, then z over the
-// full extent of the other directions would give.  The metric is static and
-// read at the point itself.
+// (outflow: the nearest interior point; periodic: the image; fixed: itself).
+// The stencil kernels read the stage fields (primitives, E, face fields)
+// through these maps, so their ghost points need no fill: a read at a ghost
+// point goes to the point whose value the rule gives it (fixed ghost points
+// hold their initial values, set at initialisation and never written; the
+// one layer of stage E next to the interior, which the cell pass's charge
+// reads with plain offsets, is written by the face update).  Composing the
+// maps of x, y and z gives the values that filling the ghost points along x,
+// then y, then z over the full extent of the other directions would give.
+// The metric is static and read at the point itself.
 
 // index along d of the cell whose stage value cell m takes (m inside the
 // padded box; m itself inside the interior and along an inactive direction)

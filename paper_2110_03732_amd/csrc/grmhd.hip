@@ -1809,8 +1809,7 @@ gr_status gr_init_state(const gr_grid *g, gr_state *st, const double *prim_host,
         HIPCHK(hipMemsetAsync(st->q + 8 * G.fs, 0, 2 * G.fs * sizeof(double), s));
     }
     // every stage block starts as a copy of the state (ghost points of fixed
-    // boundaries keep these values: no kernel writes a ghost point of a stage
-    // field)
+    // boundaries keep these values: no kernel writes them)
     for (int j = 0; j < T.s; j++) {
         double *spj = wfield(st, G, Ly.sprim + (size_t)Ly.nsp * j);
         hipLaunchKernelGGL(k_stage_copy, gr, bl, 0, s, G, g->metric, cptrs<5>(st->prim, G.fs), cptrs<8>(st->q, G.fs),

@@ -21,9 +21,10 @@ namespace gr {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
-// No kernel writes a ghost point of a stage field: every read of a stage
-// field at a point beyond the interior goes where the boundary rule puts it
-// (stage_cell, common.h).
+// There is no ghost fill: a read of a stage field at a point beyond the
+// interior goes where the boundary rule puts it (stage_cell, common.h); only
+// the layer of stage E next to the interior, which the cell pass's charge
+// reads with plain offsets, is written (by the face update).
 
 // ---------------------------------------------------------------------------
 // HLL flux at one face of direction D from the reconstructed states of the
