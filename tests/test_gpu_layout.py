@@ -148,7 +148,17 @@ GHOST_CASES = {
     "shock_tube_1d_101_ppm_ssp3": lambda: W.shock_tube(101, recon=W.PPM, imex=W.SSP3),
     "glm_monopole_2d_33": lambda: W.glm_monopole(33, kappa=5.0, ndim=2),
     "dynamo_1d_periodic": lambda: W.steady_dynamo(64, k=1),
+    # periodic as small as the ghost width, a one-cell-thick active
+    # direction, ragged tiles in every direction
+    "box_3d_3x3x3_periodic_ppm_ssp3": lambda: _parity_case("box_3d_3x3x3_periodic_ppm_ssp3"),
+    "box_3d_12x9x1_outflow_mc": lambda: _parity_case("box_3d_12x9x1_outflow_mc"),
+    "star_13x11x9_ragged": lambda: _parity_case("star_13x11x9_ragged"),
 }
+
+
+def _parity_case(name):
+    import test_gpu_parity
+    return test_gpu_parity.CASES[name]()
 
 
 def _ghost_mask(run, face_dir=None):
