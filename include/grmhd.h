@@ -160,11 +160,12 @@ gr_status gr_init_state(const gr_grid *grid, gr_state *state, const double *prim
  * points of fixed boundaries keep the values they were initialised with (in
  * the workspace, a pass with L writes the layer of stage E next to the
  * interior, which its cell pass reads for the Gauss-law charge).
- * In a pass that evaluates L on a grid of at least 2^20 interior cells, the
- * edge-EMF and face-update launches run on a second stream the library owns
- * (one per device, default priority, created by gr_init_state), forked from
- * `stream` with an event at the start of the pass and joined back before the
- * cell pass: the call stays ordered on `stream` and can be captured into a graph
+ * In a pass that evaluates L on a grid of at least 2^20 interior cells (2^18
+ * while `stream` is being captured into a graph), the edge-EMF and
+ * face-update launches run on a second stream the library owns (one per
+ * device, default priority, created by gr_init_state), forked from `stream`
+ * with an event at the start of the pass and joined back before the cell
+ * pass: the call stays ordered on `stream` and can be captured into a graph
  * from it.  Smaller grids launch everything on `stream`.  The second stream
  * is shared by every call on the device: forked calls from several host
  * threads queue their EMF launches on it one after another, and a call being
@@ -296,16 +297,18 @@ gr_status gr_batch_update(gr_batch *batch, const gr_grid *grids, const gr_state 
                           int nruns, hipStream_t stream);
 
 /* One step of every run, launched eagerly on the stream.  When the runs
- * hold at least 2^20 interior cells together, the EMF and face-update
- * launches of each pass run on a second stream the batch owns (created by
- * gr_batch_create, default priority) beside the x/y sweeps, forked from and
- * joined back into `stream` as in gr_imex_stage. */
+ * hold at least 2^20 interior cells together (2^18 while `stream` is being
+ * captured), the EMF and face-update launches of each pass run on a second
+ * stream the batch owns (created by gr_batch_create, default priority)
+ * beside the x/y sweeps, forked from and joined back into `stream` as in
+ * gr_imex_stage. */
 gr_status gr_batch_step(gr_batch *batch, hipStream_t stream);
 
 /* nsteps steps of every run: on the first call the step is captured into a
  * HIP graph (on a capture stream the batch creates; the launches are never
- * executed there) and the graph is then launched nsteps times on the given
- * stream, which may be the null stream.  Asynchronous. */
+ * executed there; the fork to the batch's second stream from 2^18 cells)
+ * and the graph is then launched nsteps times on the given stream, which may
+ * be the null stream.  Asynchronous. */
 gr_status gr_batch_run(gr_batch *batch, int nsteps, hipStream_t stream);
 
 /* Launches per step, algorithmic bytes per step (summed over runs, same

@@ -534,15 +534,29 @@ void with_ct(int K, int F, Fn &&f)
 // Everything one pass of one run launches, in launch order: x/y phases, the
 // three EMF components, the face update, the cell pass.
 // a pass forks its EMF and face-update launches to the side stream only on
-// grids of at least this many cells: on smaller ones the two extra stream
-// dependencies cost more than the overlap gains (a 512^2 plane ran 8% slower
-// with the fork, and small grids on several caller streams would all queue on
-// the one side stream)
+// grids of at least kForkCells cells, or kForkCellsGraph cells while its
+// stream is being captured.  Eager, the fork and the join are host calls on
+// each pass, and on a 512^2 plane (launch-bound) they cost more than the
+// overlap gains (8% slower); small grids on several caller streams would also
+// all queue on the one side stream.  In a graph they are two dependency
+// edges and the plane runs 6% faster with them (768^2: 12%).
 constexpr long kForkCells = 1L << 20;
+constexpr long kForkCellsGraph = 1L << 18;
+bool fork_wanted(long cells, hipStream_t s)
+{
+    if (cells >= kForkCells) return true;
+    if (cells < kForkCellsGraph) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs == hipStreamCaptureStatusActive;
+}
 
 struct PassPlan {
     bool xy = false, face = false;
-    bool fork = false;  // EMFs and face update beside the sweeps
+    long cells = 0;  // interior cells of the grid
     bool swz = false;  // cell pass with the z phase
     bool ct[3] = {false, false, false};
     int ctf[3] = {CT_BOX, CT_BOX, CT_BOX};  // EMF kernel form per launch
@@ -571,7 +585,7 @@ gr_status plan_pass(const gr_grid *g, gr_state *st, int p, double dt, const Vari
     Tableau T = tableau(g->imex);
     Layout Ly = layout(g);
     if (p < 0 || p > T.s) return GR_EINVAL;
-    pl.fork = (long)G.n[0] * G.n[1] * G.n[2] >= kForkCells;
+    pl.cells = (long)G.n[0] * G.n[1] * G.n[2];
     const int MET = V.met;
     const bool fin = (p == T.s);
     const bool withL = (p >= 1) && needL(T, p - 1);
@@ -827,6 +841,23 @@ gr_status side_stream(hipStream_t *out)
     return GR_OK;
 }
 
+// fork and join events of the calling host thread on the current device,
+// created on first use and kept: a wait refers to the record made just
+// before it, so one pair serves every pass (per thread, so that two threads
+// forking on one device at once never re-record each other's events)
+thread_local hipEvent_t t_fork_ev[64][2] = {};
+gr_status fork_events(hipEvent_t *fork, hipEvent_t *join)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return GR_EHIP;
+    for (int k = 0; k < 2; k++)
+        if (!t_fork_ev[dev][k]) HIPCHK(hipEventCreateWithFlags(&t_fork_ev[dev][k], hipEventDisableTiming));
+    *fork = t_fork_ev[dev][0];
+    *join = t_fork_ev[dev][1];
+    return GR_OK;
+}
+
 gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
 {
     // The EMFs and the face update depend only on the stage block of the
@@ -838,19 +869,12 @@ gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
     for (int i = 0; i < 3; i++) ct_any |= pl.ct[i] != 0;
     hipStream_t s2 = s;
     hipEvent_t fork = nullptr, join = nullptr;
-    if (pl.fork && pl.xy && ct_any) {
+    if (pl.xy && ct_any && fork_wanted(pl.cells, s)) {
         gr_status e = side_stream(&s2);
+        if (e == GR_OK) e = fork_events(&fork, &join);
         if (e != GR_OK) return e;
-        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-        if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
-            (void)hipEventDestroy(fork);
-            return GR_EHIP;
-        }
-        if (hipEventRecord(fork, s) != hipSuccess || hipStreamWaitEvent(s2, fork, 0) != hipSuccess) {
-            (void)hipEventDestroy(fork);
-            (void)hipEventDestroy(join);
-            return GR_EHIP;
-        }
+        HIPCHK(hipEventRecord(fork, s));
+        HIPCHK(hipStreamWaitEvent(s2, fork, 0));
     }
     for (int i = 0; i < 3; i++) {
         if (!pl.ct[i]) continue;
@@ -863,24 +887,13 @@ gr_status launch_plan(const Variant &V, const PassPlan &pl, hipStream_t s)
         hipLaunchKernelGGL(k_face_update, d3(pl.fa.gd), dim3(kBlock), 0, s2, pl.fa);
         LAUNCHCHK();
     }
-    if (join) {
-        const bool ok = hipEventRecord(join, s2) == hipSuccess;
-        (void)hipEventDestroy(fork);
-        if (!ok) {
-            (void)hipEventDestroy(join);
-            return GR_EHIP;
-        }
-    }
+    if (join) HIPCHK(hipEventRecord(join, s2));
     if (pl.xy) {
         TScope ts(KC_SWEEP, s, pl.xy_bytes);
         launch_xy(V, pl.xya, s);
         LAUNCHCHK();
     }
-    if (join) {
-        const bool ok = hipStreamWaitEvent(s, join, 0) == hipSuccess;
-        (void)hipEventDestroy(join);
-        if (!ok) return GR_EHIP;
-    }
+    if (join) HIPCHK(hipStreamWaitEvent(s, join, 0));
     {
         TScope ts(KC_CELL_UPDATE, s, pl.ca_bytes);
         launch_cell(V, pl.swz, pl.ca, s);
@@ -983,6 +996,7 @@ struct gr_batch {
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
     hipStream_t side = nullptr;  // the batch's own stream for the EMF and face-update launches
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;  // its fork and join events
     double bytes_step = 0.0;
     long cells = 0;
 };
@@ -1279,11 +1293,13 @@ gr_status launch_b(const BLaunch &L, hipStream_t s)
 // The list holds, per pass, x/y sweeps, EMFs and the face update (which all
 // depend only on the stage block of the previous pass), then the cell
 // launches.
-// With a side stream (a batch of at least kForkCells cells), as in the plain
-// path, where a pass has both sweeps and EMF / face-update launches, the
-// latter go to the side stream, forked at the start of the pass, and the cell
-// launches wait for them.  side == nullptr: everything on s.
-gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, hipStream_t side)
+// With a side stream (a batch of as many cells as fork_wanted asks for), as
+// in the plain path, where a pass has both sweeps and EMF / face-update
+// launches, the latter go to the side stream, forked at the start of the
+// pass, and the cell launches wait for them.  side == nullptr: everything on
+// s.
+gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, hipStream_t side, hipEvent_t fork_ev,
+                      hipEvent_t join_ev)
 {
     auto one = [](const BLaunch &L, hipStream_t st) {
         TScope ts(L.cls, st, L.bytes);
@@ -1305,20 +1321,12 @@ gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, hipStream_t
             sd |= on_side(ls[j].cls);
         }
         hipStream_t s2 = s;
-        hipEvent_t fork = nullptr, join = nullptr;
+        hipEvent_t join = nullptr;
         if (side && sw && sd) {
             s2 = side;
-            HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-            if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
-                (void)hipEventDestroy(fork);
-                return GR_EHIP;
-            }
-            const bool ok = hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(s2, fork, 0) == hipSuccess;
-            (void)hipEventDestroy(fork);
-            if (!ok) {
-                (void)hipEventDestroy(join);
-                return GR_EHIP;
-            }
+            join = join_ev;
+            HIPCHK(hipEventRecord(fork_ev, s));
+            HIPCHK(hipStreamWaitEvent(s2, fork_ev, 0));
         }
         gr_status e = GR_OK;
         for (size_t k = i; k < j && e == GR_OK; k++)
@@ -1331,10 +1339,7 @@ gr_status launch_list(const std::vector<BLaunch> &ls, hipStream_t s, hipStream_t
         }
         for (size_t k = i; k < j && e == GR_OK; k++)
             if (ls[k].cls == KC_SWEEP) e = one(ls[k], s);
-        if (join) {
-            if (hipStreamWaitEvent(s, join, 0) != hipSuccess && e == GR_OK) e = GR_EHIP;
-            (void)hipEventDestroy(join);
-        }
+        if (join && hipStreamWaitEvent(s, join, 0) != hipSuccess && e == GR_OK) e = GR_EHIP;
         if (e != GR_OK) return e;
         i = j;
     }
@@ -1401,9 +1406,9 @@ double time_list(const std::vector<BLaunch> &ls, hipStream_t s, int reps)
         return -1.0;
     }
     double ms = -1.0;
-    if (launch_list(ls, s, nullptr) == GR_OK && hipEventRecord(a, s) == hipSuccess) {
+    if (launch_list(ls, s, nullptr, nullptr, nullptr) == GR_OK && hipEventRecord(a, s) == hipSuccess) {
         bool ok = true;
-        for (int i = 0; i < reps && ok; i++) ok = launch_list(ls, s, nullptr) == GR_OK;
+        for (int i = 0; i < reps && ok; i++) ok = launch_list(ls, s, nullptr, nullptr, nullptr) == GR_OK;
         float f = 0.0f;
         if (ok && hipEventRecord(e, s) == hipSuccess && hipEventSynchronize(e) == hipSuccess &&
             hipEventElapsedTime(&f, a, e) == hipSuccess)
@@ -2105,6 +2110,11 @@ gr_status gr_batch_create(gr_batch **out, const gr_grid *grids, const gr_state *
         delete b;
         return GR_EHIP;
     }
+    if (hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming) != hipSuccess) {
+        gr_batch_destroy(b);
+        return GR_EHIP;
+    }
     b->grids.assign(grids, grids + nruns);
     b->states.assign(states, states + nruns);
     b->dt.assign(dt, dt + nruns);
@@ -2170,7 +2180,7 @@ gr_status gr_batch_update(gr_batch *b, const gr_grid *grids, const gr_state *sta
 gr_status gr_batch_step(gr_batch *b, hipStream_t s)
 {
     if (!b) return GR_EINVAL;
-    return launch_list(b->launches, s, b->cells >= kForkCells ? b->side : nullptr);
+    return launch_list(b->launches, s, fork_wanted(b->cells, s) ? b->side : nullptr, b->fork_ev, b->join_ev);
 }
 
 gr_status gr_batch_run(gr_batch *b, int nsteps, hipStream_t s)
@@ -2182,7 +2192,8 @@ gr_status gr_batch_run(gr_batch *b, int nsteps, hipStream_t s)
         hipError_t c = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         gr_status e = GR_OK;
         if (c == hipSuccess) {
-            e = launch_list(b->launches, b->cap, b->cells >= kForkCells ? b->side : nullptr);
+            e = launch_list(b->launches, b->cap, b->cells >= kForkCellsGraph ? b->side : nullptr, b->fork_ev,
+                            b->join_ev);
             c = hipStreamEndCapture(b->cap, &b->graph);
         }
         g_capturing = false;
@@ -2238,6 +2249,8 @@ gr_status gr_batch_destroy(gr_batch *b)
     }
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    if (b->join_ev) (void)hipEventDestroy(b->join_ev);
     delete b;
     return GR_OK;
 }

@@ -243,7 +243,7 @@ def test_batch_autotuner_cache(tmp_path):
 
 def test_batch_with_side_stream_fork():
     """a batch holding at least 2^20 cells runs the EMF and face-update
-    launches of each pass on the library's second stream beside the x/y
+    launches of each pass on the batch's second stream beside the x/y
     sweeps: its runs equal the same runs advanced alone (each below 2^20
     cells, so launched on one stream) to 1e-13 of each field's scale with the
     same failure counts, graph replays equal eager steps bit for bit, and the
@@ -295,5 +295,30 @@ def test_batch_with_side_stream_fork():
     for x, z in zip(ra, alone):
         _close(x, z)
         assert x.fail_count() == z.fail_count()
+    ba.close()
+    bb.close()
+
+
+def test_batch_forks_only_in_graph():
+    """a batch of 2^18 to 2^20 cells forks its EMF and face-update launches
+    only when captured (gr_batch_run), not in eager steps: the two give the
+    same runs bit for bit"""
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd
+    setups = [W.blast_wave(512, eta=1e-2), W.tov_star(48)]
+    assert 1 << 18 <= sum(s.ncells for s in setups) < 1 << 20
+    say("batch forked in graph only: %s" % [s.ncells for s in setups])
+    ra = [grmhd.Run(s, device="cuda:0") for s in setups]
+    rb = [grmhd.Run(s, device="cuda:0") for s in setups]
+    dts = [r.dt() for r in ra]
+    ba = grmhd.Batch(ra, dts)
+    bb = grmhd.Batch(rb, dts)
+    for _ in range(3):
+        ba.step()
+    bb.run(3)
+    torch.cuda.synchronize()
+    for x, y in zip(ra, rb):
+        _same(x, y)
+        assert x.fail_count() == y.fail_count()
     ba.close()
     bb.close()

@@ -1,10 +1,11 @@
 """A whole step (gr_step) captured into a HIP graph from a caller's stream.
 
-The capture holds every launch of the step; on a grid of 2^20 cells or more
+The capture holds every launch of the step; on a grid of 2^18 cells or more
 it also holds the fork of the EMF and face-update launches to the library's
-second stream and the join back.  Each replay must give the eager step's
-result bit for bit (the same kernels on the same inputs), also with eager
-work and synchronisations between the replays.
+second stream and the join back (eager steps fork from 2^20 cells, so the
+512^2 plane compares a forked graph with a one-stream eager step).  Each
+replay must give the eager step's result bit for bit (the same kernels on the
+same inputs), also with eager work and synchronisations between the replays.
 """
 import sys
 
@@ -28,13 +29,17 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("name", ["tov_star_104_forked", "blast_64_one_stream", "shock_tube_400_one_stream"])
+@pytest.mark.parametrize("name", ["tov_star_104_forked", "blast_512_forked_in_graph", "blast_64_one_stream",
+                                  "shock_tube_400_one_stream"])
 def test_captured_step_replays_equal_eager(name):
     torch = _torch()
     from paper_2110_03732_amd import grmhd
     if name.startswith("tov"):
         s = W.tov_star(104)
         assert s.ncells >= 1 << 20
+    elif name.startswith("blast_512"):
+        s = W.blast_wave(512, eta=1e-2)
+        assert 1 << 18 <= s.ncells < 1 << 20
     elif name.startswith("blast"):
         s = W.blast_wave(64, eta=1e-2)
     else:
