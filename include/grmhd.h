@@ -234,9 +234,11 @@ gr_status gr_fail_count(const gr_grid *grid, const gr_state *state, unsigned lon
  * class is set in kernel_class_mask, every launch of that class is
  * bracketed by two HIP events recorded on the stream it is launched on,
  * together with the algorithmic bytes of the launch (each live input field
- * read once, each output field written once).  gr_timing_start clears
- * earlier records; mask 0 switches recording off.  Host-side state shared by
- * all calls of the process. */
+ * read once, each output field written once).  While any bit is set, passes
+ * launch every kernel on the caller's stream (no fork to the second stream),
+ * so that each class is timed alone and not while it shares the device with
+ * another.  gr_timing_start clears earlier records; mask 0 switches
+ * recording off.  Host-side state shared by all calls of the process. */
 gr_status gr_timing_start(unsigned kernel_class_mask);
 
 /* Totals of the records of one kernel class: summed event time (ms), number

@@ -43,7 +43,9 @@ namespace {
 // ---------------------------------------------------------------------------
 // measurement hook: launches of the selected kernel classes are bracketed by
 // HIP events on the stream they are launched on, with the algorithmic bytes
-// (every live input field read once, every output written once) of the launch
+// (every live input field read once, every output written once) of the launch.
+// While it records, passes do not fork (fork_wanted), so that each class is
+// timed alone rather than while it shares the device with another.
 enum KClass { KC_SWEEP = 0, KC_CT, KC_FACE_UPDATE, KC_CELL_UPDATE, KC_COUNT };
 const char *kClassNames[KC_COUNT] = {"k_xy", "k_ct", "k_face_update", "k_cell_update"};
 struct TRec {
@@ -544,6 +546,7 @@ constexpr long kForkCells = 1L << 20;
 constexpr long kForkCellsGraph = 1L << 18;
 bool fork_wanted(long cells, hipStream_t s)
 {
+    if (g_tmask) return false;
     if (cells >= kForkCells) return true;
     if (cells < kForkCellsGraph) return false;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
