@@ -434,6 +434,14 @@ class Batch:
         gr_batch_update(self.h, [r.grid for r in self.runs], [r.state for r in self.runs], self.dts,
                         self.stream.cuda_stream)
 
+    def set_dt(self, dts):
+        """new time steps for the batch's runs (stream-ordered)"""
+        dts = [float(x) for x in dts]
+        if len(dts) != len(self.runs):
+            raise ValueError("one time step per run")
+        gr_batch_set_dt(self.h, dts, self.stream.cuda_stream)
+        self.dts = dts
+
     def step(self):
         gr_batch_step(self.h, self.stream.cuda_stream)
         for r, dt in zip(self.runs, self.dts):

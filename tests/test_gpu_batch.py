@@ -322,3 +322,51 @@ def test_batch_forks_only_in_graph():
         assert x.fail_count() == y.fail_count()
     ba.close()
     bb.close()
+
+
+def test_batch_set_dt_and_tiles():
+    """gr_batch_set_dt gives every run a new time step: the steps after it
+    equal, bit for bit, those of a batch given the same steps by
+    gr_batch_update (eager, and as a graph captured again after the change),
+    and the runs advanced alone to 1e-13; gr_batch_tiles names the tiles of
+    every run"""
+    import re
+    torch = _torch()
+    from paper_2110_03732_amd import grmhd
+    setups = [W.blast_wave(48, eta=1e-2), W.shock_tube(200, imex=W.SSP3), W.tov_star(20)]
+    say("set_dt batch: %s" % [s.ncells for s in setups])
+    ra, rb, rc, alone = ([grmhd.Run(s, device="cuda:0") for s in setups] for _ in range(4))
+    dt1 = [r.dt() for r in ra]
+    dt2 = [0.5 * d for d in dt1]
+    ba, bb, bc = grmhd.Batch(ra, dt1), grmhd.Batch(rb, dt1), grmhd.Batch(rc, dt1)
+    ba.run(2)
+    bb.run(2)
+    bc.step()
+    bc.step()
+    ba.set_dt(dt2)
+    bb.update(rb, dt2)
+    bc.set_dt(dt2)
+    ba.run(2)
+    for _ in range(2):
+        bb.step()
+        bc.step()
+    for r, d1, d2 in zip(alone, dt1, dt2):
+        for dt in (d1, d1, d2, d2):
+            r.step(dt)
+    torch.cuda.synchronize()
+    for x, y, z, w in zip(ra, rb, rc, alone):
+        _same(x, y)
+        _same(z, y)
+        _close(x, w)
+        assert x.fail_count() == w.fail_count()
+        assert abs(x.t - w.t) <= 1e-15 * w.t
+    for i in range(len(setups)):
+        for name in ba.tiles(i):
+            assert re.fullmatch(r"\d+x\d+", name), name
+    with pytest.raises(ValueError):
+        ba.set_dt(dt2[:2])
+    with pytest.raises(grmhd.GrError):  # GR_EINVAL: a step that is not positive
+        ba.set_dt([dt2[0], 0.0, dt2[2]])
+    assert ba.dts == dt2
+    for b in (ba, bb, bc):
+        b.close()
