@@ -1,6 +1,6 @@
 """ctypes wrapper of the plain-C CPU oracle (oracle/oracle.c).
 
-TEST INFRASTRUCTURE ONLY: the oracle is the checker of the HIP library.  Only
+TEST INFRASTRUCTURE ONLY: the HIP library is tested against the oracle.  Only
 the test-suite, the smoke check and the CPU-baseline leg of the benchmark may
 import this module.  It shares no code with the GPU path; the only common
 input is the seeded initial data of the `workloads` module.

@@ -5,8 +5,8 @@
  * general-relativistic resistive magnetohydrodynamics based on staggered-meshed
  * constrained transport with elliptic cleaning" (arXiv:2110.03732).
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the checker of the HIP library, not
- * part of it: only the test-suite, the smoke check and the CPU-baseline leg of
+ * TEST INFRASTRUCTURE ONLY.  The HIP library is tested against this file,
+ * which is no part of it: only the test-suite, the smoke check and the CPU-baseline leg of
  * the benchmark may load it.  It shares no code, header or table with the GPU
  * path.  Everything is FP64, evaluated in the paper's order and notation with a
  * general 3x3 spatial metric gamma_ij = psi^4 delta_ij (conformally flat,
