@@ -548,7 +548,9 @@ bool fork_wanted(long cells, hipStream_t s)
 {
     if (g_tmask) return false;
     if (cells >= kForkCells) return true;
-    if (cells < kForkCellsGraph) return false;
+    // the legacy null stream is never captured (and asking about it while
+    // another thread captures in global mode is an error)
+    if (cells < kForkCellsGraph || s == nullptr) return false;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
         (void)hipGetLastError();
