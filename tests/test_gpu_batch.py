@@ -19,6 +19,7 @@ import pytest
 import oracle
 import workloads as W
 from parity import device_E, oracle_E, state_errors
+from test_gpu_parity import _mixed_box
 
 pytestmark = pytest.mark.gpu
 
@@ -172,7 +173,8 @@ def test_batch_run_matches_oracle():
     """every kind of run the batched kernels distinguish -- 1-D/2-D SSP2
     runs, and the SSP3 mix: the 3-D star with its metric, the star on a plane
     and a line, the current sheet, the dynamo (frozen and moving), plus GLM
-    and ideal-MHD UCT runs -- advanced three steps by graph replay inside
+    and ideal-MHD UCT runs and 3-D boxes with a different boundary rule along
+    each direction -- advanced three steps by graph replay inside
     batches, element by element against the oracle (relative L1 1e-10,
     element-wise 1e-9 of each field's scale, as the one-step parity tests)"""
     torch = _torch()
@@ -181,7 +183,9 @@ def test_batch_run_matches_oracle():
     mix3 = _mix(W.SSP3)
     ideal = W.blast_wave(40, eta=1e-6, imex=W.SSP3)
     ideal.uct = 1
-    mix3 += [ideal, W.glm_monopole(33, kappa=5.0, ndim=2, imex=W.SSP3)]
+    # a different boundary rule along each direction, face fields and GLM
+    mix3 += [ideal, W.glm_monopole(33, kappa=5.0, ndim=2, imex=W.SSP3), _mixed_box(W.PPM, W.SSP3),
+             _mixed_box(W.PPM, W.SSP3, glm=True)]
     groups.append(mix3)
     for setups in groups:
         say("batch vs oracle: %d runs" % len(setups))

@@ -12,6 +12,7 @@ import pytest
 import oracle
 import workloads as W
 from parity import device_E, oracle_E, state_errors
+from test_gpu_parity import _mixed_box
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +52,9 @@ CASES = {
     "monopole_2d_37_kappa1_ppm_ssp3": lambda: W.glm_monopole(37, kappa=1.0, ndim=2, recon=W.PPM, imex=W.SSP3),
     "monopole_3d_20_kappa1": lambda: W.glm_monopole(20, kappa=1.0, ndim=3),
     "monopole_3d_19_kappa10_ppm_ssp3": lambda: W.glm_monopole(19, kappa=10.0, ndim=3, recon=W.PPM, imex=W.SSP3),
+    # periodic in x, outflow in y, fixed in z on a ragged grid of several tiles
+    "box_3d_37x15x18_mixed_bc_mc_ssp2": lambda: _mixed_box(W.MC, W.SSP2, glm=True),
+    "box_3d_37x15x18_mixed_bc_ppm_ssp3": lambda: _mixed_box(W.PPM, W.SSP3, glm=True),
 }
 
 

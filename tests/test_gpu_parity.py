@@ -60,6 +60,9 @@ CASES = {
     "box_1d_3_periodic_ppm": lambda: _smooth_box(1, (3, 1, 1), W.PERIODIC, W.PPM),
     "box_3d_3x3x3_periodic_ppm_ssp3": lambda: _smooth_box(3, (3, 3, 3), W.PERIODIC, W.PPM, W.SSP3),
     "box_2d_5x4_fixed_minmod": lambda: _smooth_box(2, (5, 4, 1), W.FIXED, W.MINMOD),
+    # a different boundary rule along each direction of a ragged 3-D grid
+    "box_3d_37x15x18_mixed_bc_ppm_ssp3": lambda: _mixed_box(W.PPM, W.SSP3),
+    "box_3d_37x15x18_mixed_bc_mc_ssp2": lambda: _mixed_box(W.MC, W.SSP2),
     # ideal-MHD edge EMF (App. A)
     "shock_tube_400_minmod_ssp2_uct_ideal": lambda: _with(W.shock_tube(400), uct=1),
     "blast_48_ppm_ssp3_stiff_uct_ideal": lambda: _with(W.blast_wave(48, eta=1e-6), uct=1),
@@ -107,6 +110,19 @@ def _smooth_box(ndim, n, bc, recon=W.MC, imex=W.SSP2):
     s.face = np.zeros((3,) + s.shape)
     for i in range(3):
         s.face[i] = B[i]
+    return s
+
+
+def _mixed_box(recon, imex, glm=False):
+    """the smooth box on a ragged 3-D grid spanning several tiles of every
+    kernel, with a different boundary rule along each direction: periodic in
+    x, outflow in y, fixed in z (GLM: cell-centred q_B and the two cleaning
+    fields in place of the face fields and the edge EMF)"""
+    s = _smooth_box(3, (37, 15, 18), W.PERIODIC, recon, imex)
+    s.bc = ((W.PERIODIC, W.PERIODIC), (W.OUTFLOW, W.OUTFLOW), (W.FIXED, W.FIXED))
+    s.name = "box_mixed"
+    if glm:
+        s.glm, s.kappa_E, s.kappa_B = 1, 1.0, 2.0
     return s
 
 
@@ -173,7 +189,7 @@ def test_one_step_parity(name):
 @pytest.mark.parametrize("name", ["shock_tube_400_minmod_ssp2", "blast_48_ppm_ssp3_eta1e-2", "star_24_cowling",
                                   "dynamo_k1_frozen_xi0.5", "blast_48_ppm_ssp3_eta1e-2_uct_ideal",
                                   "star_24_cowling_uct_ideal", "loop_periodic_40x20", "star_2d_40_cowling",
-                                  "star_1d_150_cowling"])
+                                  "star_1d_150_cowling", "box_3d_37x15x18_mixed_bc_ppm_ssp3"])
 def test_hundred_steps_parity(name):
     _torch()
     say("case %s: 100 steps" % name)
