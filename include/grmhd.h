@@ -272,9 +272,9 @@ typedef struct gr_batch gr_batch;
  * does the same for the classes not yet listed in that text file and
  * appends its decisions to it.  Allocates the argument block (hipMalloc,
  * with spare room for later updates) and its pinned host staging
- * (hipHostMalloc) and a second stream for the forked launches of
- * gr_batch_step, and synchronises the stream.  GR_EUNSUPPORTED if the runs
- * mix IMEX tableaux. */
+ * (hipHostMalloc), a second stream and two events for the forked launches
+ * of gr_batch_step and gr_batch_run, and synchronises the stream.
+ * GR_EUNSUPPORTED if the runs mix IMEX tableaux. */
 gr_status gr_batch_create(gr_batch **batch, const gr_grid *grids, const gr_state *states, const double *dt,
                           int nruns, const char *tune_cache, hipStream_t stream);
 
