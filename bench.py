@@ -161,8 +161,10 @@ def fp64_rate(kernel, avg_us):
 
 
 def kernel_roofline(run, dt, steps, grmhd, torch):
-    """replay of the timed steps with every kernel class bracketed by HIP
-    events on the run's stream; roofline of the class with the largest time"""
+    """the timed steps again with every launch of each kernel class
+    bracketed by HIP events on the stream it is launched on (while the events
+    record, the library runs each pass on one stream, so every class is
+    timed alone); roofline of the class with the largest time"""
     n_cls = 0
     while grmhd.gr_kernel_class_name(n_cls):
         n_cls += 1
