@@ -3,7 +3,8 @@ every combination the kernels distinguish (dimension, reconstruction, IMEX
 tableau, metric, boundary rule, EMF form, dynamo term, resistivity from ideal
 to diffusive) drawn from splitmix64, two steps each, primitives, E and faces
 within relative L1 1e-10 and element-wise 1e-9 of each field's scale, div B
-at round-off."""
+at round-off.  A second sweep draws ragged 3-D boxes with a boundary rule of
+their own along each direction."""
 import math
 
 import numpy as np
@@ -62,5 +63,46 @@ def test_sweep(i):
         run.step(dt)
         ref.step(dt)
     check(s, run, ref, 1e-10, 1e-9, tag="sweep %d" % i)
+    assert run.divB()[2] <= 1e-12
+    assert run.fail_count() == ref.nfail
+
+
+BCS = (W.OUTFLOW, W.PERIODIC, W.FIXED)
+
+
+def _box_case(i):
+    """a ragged 3-D box (the smooth bump, swirl and uniform field of the
+    parity cases) with its own boundary rule along each direction and a
+    random reconstruction, tableau, resistivity, EMF form and dynamo term"""
+    from test_gpu_parity import _smooth_box
+    u = 0.5 * (W.uniform_pm1(20261204, i, 12) + 1.0)
+    recon = RECONS[int(u[0] * 3)]
+    imex = IMEXES[int(u[1] * 2)]
+    n = (5 + int(u[2] * 17), 5 + int(u[3] * 13), 5 + int(u[4] * 15))
+    s = _smooth_box(3, n, W.OUTFLOW, recon, imex)
+    s.bc = tuple((BCS[int(u[5 + d] * 3)],) * 2 for d in range(3))
+    s.eta = math.exp(math.log(1e-6) + u[8] * (math.log(1.0) - math.log(1e-6)))
+    s.uct = int(u[9] < 0.3)
+    s.xi = 0.05 if u[10] < 0.25 else 0.0
+    s.name = "box_sweep"
+    return s
+
+
+@pytest.mark.parametrize("i", range(16))
+def test_sweep_3d_boxes(i):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2110_03732_amd import grmhd
+    s = _box_case(i)
+    print("box sweep %d: n %s bc %s recon %d imex %d uct %d xi %g eta %.2e" % (
+        i, s.n, [b[0] for b in s.bc], s.recon, s.imex, s.uct, s.xi, s.eta), flush=True)
+    run = grmhd.Run(s, device="cuda:0")
+    ref = oracle.OracleState(s)
+    dt = ref.dt()
+    for _ in range(2):
+        run.step(dt)
+        ref.step(dt)
+    check(s, run, ref, 1e-10, 1e-9, tag="box sweep %d" % i)
     assert run.divB()[2] <= 1e-12
     assert run.fail_count() == ref.nfail
