@@ -106,3 +106,31 @@ def test_sweep_3d_boxes(i):
     check(s, run, ref, 1e-10, 1e-9, tag="box sweep %d" % i)
     assert run.divB()[2] <= 1e-12
     assert run.fail_count() == ref.nfail
+
+
+def test_sweep_3d_boxes_batched():
+    """the 16 boxes of the box sweep advanced two steps inside two batches
+    (one per IMEX tableau, replayed graphs), each against the oracle at the
+    same bars"""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2110_03732_amd import grmhd
+    cases = [_box_case(i) for i in range(16)]
+    for imex in IMEXES:
+        setups = [s for s in cases if s.imex == imex]
+        print("batched box sweep: imex %d, %d runs" % (imex, len(setups)), flush=True)
+        runs = [grmhd.Run(s, device="cuda:0") for s in setups]
+        dts = [r.dt() for r in runs]
+        b = grmhd.Batch(runs, dts)
+        b.run(2)
+        torch.cuda.synchronize()
+        for s, r, dt in zip(setups, runs, dts):
+            ref = oracle.OracleState(s)
+            assert dt == pytest.approx(ref.dt(), rel=1e-14)
+            for _ in range(2):
+                ref.step(dt)
+            check(s, r, ref, 1e-10, 1e-9, tag="batched box n %s bc %s" % (s.n, [x[0] for x in s.bc]))
+            assert r.divB()[2] <= 1e-12
+            assert r.fail_count() == ref.nfail
+        b.close()
