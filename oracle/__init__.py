@@ -16,6 +16,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "oracle.c")
+# the planted-mistake tests point the wrapper at a modified copy of the
+# source; its library is built beside that copy
+if os.environ.get("GR_ORACLE_SRC"):
+    SRC_PATH = os.path.abspath(os.environ["GR_ORACLE_SRC"])
+    LIB_PATH = os.path.join(os.path.dirname(SRC_PATH), "liboracle.so")
 
 
 def build(force=False):

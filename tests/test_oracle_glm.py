@@ -5,7 +5,8 @@ B'' + kappa B' + k^2 B = 0 (the GLM equations with v = 0 and Phi(0) = 0:
 a(t) = a_0 e^{-kappa t/2} [cos(w t) + kappa/(2w) sin(w t)], w^2 = k^2 -
 kappa^2/4); the paper's statement that the monopole damping grows with kappa
 (Sec 5.1: kappa = 1, 5, 10); a uniform magnetised state keeps Psi = Phi = 0
-and stays uniform."""
+and stays uniform; uniform Psi and Phi of a state at rest decay by the
+explicit stability polynomial at -kappa_E dt and -kappa_B dt."""
 import math
 
 import numpy as np
@@ -75,3 +76,37 @@ def test_glm_uniform_state_stays():
         assert np.ptp(st.face[d][sl]) <= 1e-13
     for v_ in range(5):
         assert np.ptp(st.prim[v_][sl]) <= 1e-12 * max(1.0, np.abs(st.prim[v_][sl]).max())
+
+
+@pytest.mark.parametrize("imex", [W.SSP2, W.SSP3])
+def test_uniform_psi_phi_decay_at_the_explicit_rate(imex):
+    """a uniform state at rest with E = B = 0 and uniform Psi, Phi: every
+    flux and every other source vanishes, and the damping terms of Sec 3.1
+    are explicit sources, so each step multiplies Psi by the stability
+    polynomial of the explicit tableau at z = -kappa_E dt and Phi by the same
+    polynomial at z = -kappa_B dt: 1 + z + z^2/2 (IMEX-SSP2(2,2,2)),
+    1 + z + z^2/2 + z^3/6 (IMEX-SSP3(4,3,3), whose explicit part is third
+    order)"""
+    s = W.glm_wave(16, k=1, kappa=1.0, imex=imex)
+    s.kappa_E, s.kappa_B = 2.0, 5.0
+    s.frozen_matter = 0
+    s.face[:] = 0.0
+    st = oracle.OracleState(s)
+    psi0, phi0 = 0.3, -0.2
+    st.q[8][...] = psi0
+    st.q[9][...] = phi0
+    dt = st.dt()
+
+    def R(z):
+        r = 1.0 + z + z * z / 2.0
+        return r + z ** 3 / 6.0 if imex == W.SSP3 else r
+
+    sl = s.interior
+    for n in range(1, 11):
+        st.step(dt)
+        for v, a0, kap in ((8, psi0, s.kappa_E), (9, phi0, s.kappa_B)):
+            ex = a0 * R(-kap * dt) ** n
+            got = st.q[v][sl]
+            assert np.abs(got - ex).max() <= 1e-13 * abs(ex), (n, v)
+    for v in range(5):
+        assert np.ptp(st.prim[v][sl]) == 0.0

@@ -1,0 +1,139 @@
+"""Planted mistakes in the oracle, on the CPU.
+
+Each case copies oracle/oracle.c with one plausible mistake (a dropped term,
+a flipped sign, a wrong coefficient, weight or index), builds that copy into
+its own library and runs the pin that should notice it: every copy must fail
+its pin, and the unmodified copy must pass all of them.  The pins compare
+with closed forms, printed values and invariants, not with the oracle's own
+formulas, so this shows that a mistake in each of these parts of the method
+would not go unseen.  A copy counts as caught only when its pin fails an
+assertion (a copy that does not build, or a test that errors, does not
+count)."""
+import concurrent.futures
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+SP = "tests/test_oracle_spatial.py::"
+RU = "tests/test_oracle_rules.py::"
+IM = "tests/test_oracle_imex.py::"
+PT = "tests/test_oracle_point.py::"
+GL = "tests/test_oracle_glm.py::"
+UI = "tests/test_oracle_uct_ideal.py::"
+DY = "tests/test_oracle_dynamo.py::"
+
+# (what is planted, the text it replaces, the replacement, the pin)
+MUTATIONS = [
+    ("HLL dissipation with the wrong sign (Sec 2.5)",
+     "F[v] = (cp * fL[v] + cm * fR[v] - cp * cm * (qR[v] - qL[v])) / (cp + cm);",
+     "F[v] = (cp * fL[v] + cm * fR[v] + cp * cm * (qR[v] - qL[v])) / (cp + cm);",
+     DY + "test_printed_growth_k1"),
+    ("upwind EMF jump of q_B^b reversed (Sec 3.2 (vii))",
+     "cap * cam / (cap + cam) * (qbR - qbL) - cbp * cbm / (cbp + cbm) * (qaR - qaL);",
+     "cap * cam / (cap + cam) * (qbL - qbR) - cbp * cbm / (cbp + cbm) * (qaR - qaL);",
+     DY + "test_printed_growth_k1"),
+    ("edge lapse replaced by 1 (Sec 3.2 (v))",
+     "double ae = asum / na;", "double ae = 1.0 + 0.0 * asum / na;",
+     SP + "test_constant_metric_is_a_rescaled_flat_run"),
+    ("non-stiff current rho_e v with the wrong sign (Sec 2.1)",
+     "for (int a = 0; a < 3; a++) L[5 + a] += -al * m.sqrtg * rhoe * v[a];\n                for (int vv",
+     "for (int a = 0; a < 3; a++) L[5 + a] += al * m.sqrtg * rhoe * v[a];\n                for (int vv",
+     SP + "test_gauss_charge_current_closed_form"),
+    ("metric-derivative source of S_i dropped (Sec 2.1)",
+     "sg += 0.5 * al * Sjk[jj][kk] * dg;", "sg += 0.0 * al * Sjk[jj][kk] * dg;",
+     SP + "test_tov_hydrostatic_residual_converges"),
+    ("energy source s_tau dropped (Sec 2.1)",
+     "L[4] += m.sqrtg * st;", "L[4] += 0.0 * st;",
+     SP + "test_killing_energy_in_static_lapse"),
+    ("IMEX-SSP3(4,3,3) explicit coefficient a~_31 mistyped (Sec 2.3)",
+     "At[3 * 4 + 1] = 0.25;", "At[3 * 4 + 1] = 0.26;",
+     IM + "test_ssp3_order_conditions"),
+    ("PPM interface weight 1/6 for 1/12",
+     "double v = 7.0 / 12.0 * (a0 + a1) - 1.0 / 12.0 * (am1 + a2);",
+     "double v = 7.0 / 12.0 * (a0 + a1) - 1.0 / 6.0 * (am1 + a2);",
+     IM + "test_recon_exact_on_linear_data"),
+    ("PPM steepening threshold d^2/3 for d^2/6",
+     "if (d * mm > d * d / 6.0) *aL = 3.0 * a - 2.0 * *aR;",
+     "if (d * mm > d * d / 3.0) *aL = 3.0 * a - 2.0 * *aR;",
+     IM + "test_recon_reflection_symmetry_and_bounds"),
+    ("eq. im_E coefficient A_1 without its factor W (Sec 2.4)",
+     "c->A[1] = et / opW + x2 * et * W / (Wpe * opW);", "c->A[1] = et / opW + x2 * et / (Wpe * opW);",
+     PT + "test_im_E_coefficients_match_direct_solve"),
+    ("eq. im_E coefficient A_2 with the wrong sign (Sec 2.4)",
+     "c->A[2] = -xi * et / Wpe;", "c->A[2] = xi * et / Wpe;",
+     PT + "test_im_E_coefficients_match_direct_solve"),
+    ("GLM damping kappa_E of Psi dropped (Sec 3.1)",
+     "L[11] += m.sqrtg * (al * rhoe - al * G->kappa_E * Psi + Eda);", "L[11] += m.sqrtg * (al * rhoe + Eda);",
+     GL + "test_uniform_psi_phi_decay_at_the_explicit_rate"),
+    ("GLM damping kappa_B of Phi with the wrong sign (Sec 3.1)",
+     "L[12] += m.sqrtg * (-al * G->kappa_B * Phi + Bda);", "L[12] += m.sqrtg * (al * G->kappa_B * Phi + Bda);",
+     GL + "test_glm_wave_closed_form"),
+    ("ideal-MHD EMF: face velocities weighted by the wrong sides (App. A)",
+     "return (cm * vR + cp * vL) / (cm + cp);", "return (cm * vL + cp * vR) / (cm + cp) + 1e-3 * (vR - vL);",
+     UI + "test_ideal_uct_blast_wave_mirror_symmetry"),
+    ("ideal-MHD EMF: b-direction term with the wrong sign (App. A)",
+     "return -t1 + t2;", "return -t1 - t2;",
+     UI + "test_linear_field_face_update_exact"),
+    ("E of a cell at rest with the wrong relaxation factor (R23b)",
+     "for (int i = 0; i < 3; i++) E[i] = (Es[i] + xi * r * B[i]) / (1.0 + r);",
+     "for (int i = 0; i < 3; i++) E[i] = (Es[i] + xi * r * B[i]) / (1.0 + 2.0 * r);",
+     RU + "test_fallback_state_field_and_count"),
+    ("atmosphere pressure set to the atmosphere density (R18)",
+     "prim[4] = G->p_atm;", "prim[4] = G->rho_atm;",
+     RU + "test_fallback_state_field_and_count"),
+    ("resistivity not clamped at eta_min (eq. sigma_D)",
+     "return e < G->eta_min ? G->eta_min : e;", "return e;",
+     RU + "test_eta_of_D_from_relaxation"),
+    ("outflow ghost copied from the second interior cell (R17)",
+     "s[d] = (bc == BC_PERIODIC) ? m + n : g;\n                        } else {",
+     "s[d] = (bc == BC_PERIODIC) ? m + n : g + 1;\n                        } else {",
+     RU + "test_ghost_fill_rules"),
+    ("CFL rate not summed over directions (R16)",
+     "s += al * sqrt(1.0 / pow4(ps)) / q.dx[d];", "s = al * sqrt(1.0 / pow4(ps)) / q.dx[d];",
+     RU + "test_cfl_dt_flat_closed_form"),
+]
+
+
+def _run(workdir, text, pins):
+    os.makedirs(workdir, exist_ok=True)
+    src = os.path.join(workdir, "oracle.c")
+    with open(src, "w") as f:
+        f.write(text)
+    # build the copy first (the same command as oracle.build): a copy that
+    # does not compile is reported as such, never as caught
+    b = subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o",
+                        os.path.join(workdir, "liboracle.so"), src, "-lm"], capture_output=True, text=True)
+    if b.returncode != 0:
+        return -1, "build failed:\n" + b.stderr[-2000:]
+    env = dict(os.environ, GR_ORACLE_SRC=src, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"] + pins,
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    return r.returncode, r.stdout[-3000:]
+
+
+def test_planted_mistakes_fail_their_pins(tmp_path):
+    base = open(SRC).read()
+    for what, old, new, pin in MUTATIONS:
+        assert base.count(old) >= 1, "no longer in the oracle: %s" % what
+    pins = sorted({m[3] for m in MUTATIONS})
+    jobs = [("unmodified", base, pins)] + [(m[0], base.replace(m[1], m[2], 1), [m[3]]) for m in MUTATIONS]
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        futs = [ex.submit(_run, str(tmp_path / ("m%d" % i)), text, p) for i, (_, text, p) in enumerate(jobs)]
+        res = [f.result() for f in futs]
+    rc0, out0 = res[0]
+    assert rc0 == 0, "the unmodified oracle fails its pins:\n" + out0
+    def caught(rc, out):
+        tail = out.strip().splitlines()[-1] if out.strip() else ""
+        return rc == 1 and " failed" in tail and " error" not in tail
+
+    missed = [jobs[i][0] for i in range(1, len(jobs)) if not caught(*res[i])]
+    for i in range(1, len(jobs)):
+        print("%-8s %s" % ("caught" if caught(*res[i]) else "MISSED", jobs[i][0]))
+    assert not missed, missed
