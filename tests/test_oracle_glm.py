@@ -110,3 +110,52 @@ def test_uniform_psi_phi_decay_at_the_explicit_rate(imex):
             assert np.abs(got - ex).max() <= 1e-13 * abs(ex), (n, v)
     for v in range(5):
         assert np.ptp(st.prim[v][sl]) == 0.0
+
+
+def _frozen_line(n):
+    """1-D GLM grid of a frozen fluid at rest, B = E = 0, outflow, with an
+    Ohmic resistivity so large that E does not relax over the run"""
+    s = W.glm_wave(n, k=1, kappa=1.0)
+    s.bc = ((W.OUTFLOW, W.OUTFLOW), (W.OUTFLOW, W.OUTFLOW), (W.OUTFLOW, W.OUTFLOW))
+    s.face[:] = 0.0
+    s.eta = 1e12
+    return s
+
+
+def test_lapse_gradient_sources_balance_the_fluxes():
+    """uniform E^x and B^x in a lapse linear in x (conformal factor 1): the
+    divergences of the fluxes alpha q_E and alpha q_B of Psi and Phi are
+    E^x d_x alpha and B^x d_x alpha, which the sources E^i d_i alpha and
+    B^i d_i alpha of Sec 3.1 cancel, so Psi and Phi stay zero (the face
+    lapse is the mean of two cells and the source uses the central
+    difference: both exact for a linear lapse)"""
+    s = _frozen_line(48)
+    X = s.mesh()[0]
+    s.metric = 1
+    s.alpha = 1.0 + 0.05 * X
+    s.psi = np.ones(s.shape)
+    s.E[0] = 0.3
+    s.face[0] = 0.2
+    st = oracle.OracleState(s)
+    dt = st.dt()
+    sl = s.interior
+    for _ in range(5):
+        st.step(dt)
+        assert np.abs(st.q[8][sl]).max() <= 1e-13 and np.abs(st.q[9][sl]).max() <= 1e-13
+
+
+def test_charge_source_balances_the_divergence_of_E():
+    """E^x linear in x (flat metric): the flux divergence of q_Psi is d_x E^x,
+    which the source alpha rho_e (rho_e = div E, Gauss's law) cancels, so Psi
+    stays zero away from the outflow ends (where E stops being linear)"""
+    s = _frozen_line(96)
+    X = s.mesh()[0]
+    s.E[0] = 0.1 + 0.02 * X
+    st = oracle.OracleState(s)
+    dt = st.dt()
+    g = s.g(0)
+    mid = (slice(None), slice(None), slice(g + 36, g + 60))
+    for _ in range(3):
+        st.step(dt)
+    assert np.abs(st.q[8][mid]).max() <= 1e-13
+    assert np.abs(st.E()[0][mid] - (0.1 + 0.02 * X[mid])).max() <= 1e-13

@@ -97,6 +97,79 @@ MUTATIONS = [
     ("CFL rate not summed over directions (R16)",
      "s += al * sqrt(1.0 / pow4(ps)) / q.dx[d];", "s = al * sqrt(1.0 / pow4(ps)) / q.dx[d];",
      RU + "test_cfl_dt_flat_closed_form"),
+    ("minmod picks the larger slope",
+     "return (fabs(a) < fabs(b)) ? a : b;", "return (fabs(a) > fabs(b)) ? a : b;",
+     IM + "test_recon_reflection_symmetry_and_bounds"),
+    ("minmod right state extrapolated to the wrong side",
+     "*R = w[3] - 0.5 * minmod2(w[3] - w[2], w[4] - w[3]);", "*R = w[3] + 0.5 * minmod2(w[3] - w[2], w[4] - w[3]);",
+     IM + "test_recon_exact_on_linear_data"),
+    ("MC centred slope without its 1/2",
+     "return minmod3(0.5 * (r - l), 2.0 * (c - l), 2.0 * (r - c));",
+     "return minmod3((r - l), 2.0 * (c - l), 2.0 * (r - c));",
+     DY + "test_printed_growth_k1"),
+    ("MC one-sided slope factor 1 for 2",
+     "return minmod3(0.5 * (r - l), 2.0 * (c - l), 2.0 * (r - c));",
+     "return minmod3(0.5 * (r - l), 1.0 * (c - l), 2.0 * (r - c));",
+     DY + "test_closed_form_growth_k2"),
+    ("PPM interface value not clipped between its neighbours",
+     "    if (v < lo) v = lo;\n    if (v > hi) v = hi;\n    return v;", "    (void)lo;\n    (void)hi;\n    return v;",
+     IM + "test_recon_reflection_symmetry_and_bounds"),
+    ("CT face update with the wrong sign (eq. ct)",
+     "Lf[d][id] = -s;", "Lf[d][id] = s;",
+     DY + "test_printed_growth_k1"),
+    ("CT face update with transposed Levi-Civita indices (eq. ct)",
+     "double e = levi(d, m, kk);", "double e = levi(m, d, kk);",
+     DY + "test_printed_growth_k1"),
+    ("periodic ghost image one cell off (R17)",
+     "s[d] = (bc == BC_PERIODIC) ? m + n : g;\n                        } else {",
+     "s[d] = (bc == BC_PERIODIC) ? m + n - 1 : g;\n                        } else {",
+     DY + "test_printed_growth_k1"),
+    ("stage faces built with the implicit weights (Sec 2.3)",
+     "for (int j = 0; j < i; j++) acc += dt * At[i * 4 + j] * Lf[j][d][id];",
+     "for (int j = 0; j < i; j++) acc += dt * A[i * 4 + j] * Lf[j][d][id];",
+     DY + "test_printed_growth_k1"),
+    ("final face update missing the last stage (Sec 2.3)",
+     "for (int j = 0; j < s; j++) acc += dt * wt[j] * Lf[j][d][id];",
+     "for (int j = 0; j < s - 1; j++) acc += dt * wt[j] * Lf[j][d][id];",
+     DY + "test_printed_growth_k1"),
+    ("final weight of the last SSP3 stage dropped (Sec 2.3)",
+     "for (int i = 0; i < 4; i++) w[i] = wt[i];", "for (int i = 0; i < 3; i++) w[i] = wt[i];",
+     IM + "test_ssp3_order_conditions"),
+    ("IMEX-SSP2(2,2,2) gamma 1 - 1/sqrt(3) (Table imex_ssp2)",
+     "double g = 1.0 - 1.0 / sqrt(2.0);", "double g = 1.0 - 1.0 / sqrt(3.0);",
+     IM + "test_ssp2_tableau_is_the_printed_one"),
+    ("implicit stage without the lapse in eta~ (Sec 2.4)",
+     "double etat = eta / (al * aii * dt);", "double etat = eta / (aii * dt);",
+     IM + "test_stiff_relaxation_amplification"),
+    ("frozen-matter E without the lapse in eta~ (Sec 5.7)",
+     "or_implicit_E(ps, eta / (al * aii * dt), G->xi, ut, Es, B, E);",
+     "or_implicit_E(ps, eta / (aii * dt), G->xi, ut, Es, B, E);",
+     SP + "test_constant_metric_is_a_rescaled_flat_run"),
+    ("Gauss-law charge from psi^4 E instead of q_E = psi^6 E (Sec 2.1)",
+     "double qEp = pow6(P_at(&c, ip)) * E[d][ip], qEm = pow6(P_at(&c, im)) * E[d][im];\n                    divqE",
+     "double qEp = pow4(P_at(&c, ip)) * E[d][ip], qEm = pow4(P_at(&c, im)) * E[d][im];\n                    divqE",
+     SP + "test_constant_metric_is_a_rescaled_flat_run"),
+    ("eq. im_E dynamo coefficient A_3 without (1 + W) (Sec 2.4)",
+     "c->A[3] = xi * opW / Wpe;", "c->A[3] = xi / Wpe;",
+     DY + "test_printed_growth_k1"),
+    ("eq. im_E dynamo coefficient A_4 without xi^2 (Sec 2.4)",
+     "c->A[4] = xi * (1.0 - et * et + x2) / (Wpe * opW);", "c->A[4] = xi * (1.0 - et * et) / (Wpe * opW);",
+     PT + "test_im_E_coefficients_match_direct_solve"),
+    ("recovery: internal energy with the wrong pressure sign (Sec 2.6)",
+     "double rhoeps = (tauf + D * (1.0 - W) + p * (1.0 - W * W)) / (W * W);",
+     "double rhoeps = (tauf + D * (1.0 - W) - p * (1.0 - W * W)) / (W * W);",
+     PT + "test_prim_cons_round_trip"),
+    ("GLM source E^i d_i alpha of Psi dropped (Sec 3.1)",
+     "L[11] += m.sqrtg * (al * rhoe - al * G->kappa_E * Psi + Eda);",
+     "L[11] += m.sqrtg * (al * rhoe - al * G->kappa_E * Psi);",
+     GL + "test_lapse_gradient_sources_balance_the_fluxes"),
+    ("GLM source B^i d_i alpha of Phi dropped (Sec 3.1)",
+     "L[12] += m.sqrtg * (-al * G->kappa_B * Phi + Bda);", "L[12] += m.sqrtg * (-al * G->kappa_B * Phi);",
+     GL + "test_lapse_gradient_sources_balance_the_fluxes"),
+    ("GLM charge source alpha rho_e of Psi dropped (Sec 3.1)",
+     "L[11] += m.sqrtg * (al * rhoe - al * G->kappa_E * Psi + Eda);",
+     "L[11] += m.sqrtg * (-al * G->kappa_E * Psi + Eda);",
+     GL + "test_charge_source_balances_the_divergence_of_E"),
 ]
 
 

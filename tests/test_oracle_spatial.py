@@ -151,15 +151,19 @@ def test_star_div_b_round_off():
 
 
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("uct", [0, 1])
-def test_constant_metric_is_a_rescaled_flat_run(uct):
+@pytest.mark.parametrize("uct,frozen", [(0, 0), (1, 0), (0, 1)])
+def test_constant_metric_is_a_rescaled_flat_run(uct, frozen):
     """constant lapse alpha and conformal factor psi: the conformally flat run
     equals a flat run on a domain psi^2 larger with time step alpha dt and
     orthonormal components psi^2 (u~, E, B) (face field q_B = psi^4 B_flat);
-    for the resistive (Sec 3.2) and the ideal-MHD (App. A) edge EMFs"""
+    for the resistive (Sec 3.2) and the ideal-MHD (App. A) edge EMFs, and
+    with the matter frozen (E from eq. im_E at the fixed velocity).  The
+    electric field has a divergence, so the Gauss-law charge current is
+    exercised as well"""
     alpha, psi = 0.8, 1.1
     sA = W.blast_wave(16, recon=W.MC, imex=W.SSP2, steps=3)
     sA.uct = uct
+    sA.frozen_matter = frozen
     sA.eta = 1e-2
     sA.metric = 1
     sA.alpha = np.full(sA.shape, alpha)
@@ -169,10 +173,12 @@ def test_constant_metric_is_a_rescaled_flat_run(uct):
     sA.prim[1] = 0.3 * np.exp(-(X ** 2 + Y ** 2))
     sA.prim[2] = -0.2 * np.exp(-(X ** 2 + Y ** 2))
     sA.E[2] = 0.05 * np.exp(-(X ** 2 + Y ** 2))
+    sA.E[0] = 0.04 * np.exp(-((X - 0.5) ** 2 + Y ** 2))
     stA = oracle.OracleState(sA)
     dtA = 0.02
     sB = W.blast_wave(16, recon=W.MC, imex=W.SSP2, steps=3)
     sB.uct = uct
+    sB.frozen_matter = frozen
     sB.eta = 1e-2
     sB.lo = (-6 * psi ** 2, -6 * psi ** 2, 0)
     sB.hi = (6 * psi ** 2, 6 * psi ** 2, 1)
