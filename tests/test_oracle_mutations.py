@@ -170,6 +170,65 @@ MUTATIONS = [
      "L[11] += m.sqrtg * (al * rhoe - al * G->kappa_E * Psi + Eda);",
      "L[11] += m.sqrtg * (-al * G->kappa_E * Psi + Eda);",
      GL + "test_charge_source_balances_the_divergence_of_E"),
+    ("GLM gradient of Psi in the E equation dropped (Sec 3.1)",
+     "L[5 + a] += -al * m.sqrtg * gPsi;", "L[5 + a] += 0.0 * gPsi;",
+     GL + "test_psi_drives_E_and_decays"),
+    ("GLM gradient of Phi in the B equation dropped (Sec 3.1)",
+     "L[8 + a] += -al * m.sqrtg * gPhi;", "L[8 + a] += 0.0 * gPhi;",
+     GL + "test_glm_wave_closed_form"),
+    ("GLM flux of q_Psi without the lapse (Sec 3.1)",
+     "ff[11] = al * p6 * E[d];", "ff[11] = p6 * E[d];",
+     GL + "test_lapse_gradient_sources_balance_the_fluxes"),
+    ("GLM flux of q_Phi without the lapse (Sec 3.1)",
+     "ff[12] = al * p6 * B[d];", "ff[12] = p6 * B[d];",
+     GL + "test_lapse_gradient_sources_balance_the_fluxes"),
+    ("momentum flux with twice the electromagnetic pressure (Sec 2.1)",
+     "double Sij = (p + 0.5 * (E2 + B2)) * (i == j ? 1.0 : 0.0)", "double Sij = (p + (E2 + B2)) * (i == j ? 1.0 : 0.0)",
+     SP + "test_charged_vortex_matches_paper_table"),
+    ("energy flux without -v^i D (Sec 2.1)",
+     "f[4] = m.sqrtg * alpha * (Su[i] - v[i] * D);", "f[4] = m.sqrtg * alpha * Su[i];",
+     SP + "test_star_div_b_round_off"),
+    ("flux of q_E with the wrong sign (Sec 2.1)",
+     "f[5 + j] = -m.sqrtg * s;", "f[5 + j] = m.sqrtg * s;",
+     DY + "test_printed_growth_k1"),
+    ("flux of q_D with rho for D (Sec 2.1)",
+     "f[0] = m.sqrtg * D * vhat;", "f[0] = m.sqrtg * rho * vhat;",
+     SP + "test_density_wave_second_order"),
+    ("Gauss-law charge divergence without its 1/2 (Sec 2.1)",
+     "divqE += (qEp - qEm) / (2.0 * q->dx[d]);", "divqE += (qEp - qEm) / (q->dx[d]);",
+     SP + "test_gauss_charge_current_closed_form"),
+    ("charge density without 1/psi^6 (Sec 2.1)",
+     "double rhoe = divqE / m.sqrtg;\n                for (int a = 0; a < 3; a++) L[5 + a]",
+     "double rhoe = divqE;\n                for (int a = 0; a < 3; a++) L[5 + a]",
+     SP + "test_constant_metric_is_a_rescaled_flat_run"),
+    ("W-derivative of the dynamo coefficient A_2 with the wrong sign (Sec 2.4)",
+     "c->Ad[2] = xi * et / (Wpe * Wpe);", "c->Ad[2] = -xi * et / (Wpe * Wpe);",
+     PT + "test_jacobian_matches_finite_differences"),
+    ("tau without the electric energy (Sec 2.1)",
+     "double tau = rho * h * W * W - p + 0.5 * (E2 + B2) - D;", "double tau = rho * h * W * W - p + 0.5 * (B2) - D;",
+     PT + "test_prim_cons_round_trip"),
+    ("momentum density without E x B (Sec 2.1)",
+     "for (int j = 0; j < 3; j++) q[1 + j] = m.sqrtg * (rho * h * W * W * vl[j] + ExB[j]);",
+     "for (int j = 0; j < 3; j++) q[1 + j] = m.sqrtg * (rho * h * W * W * vl[j]);",
+     PT + "test_prim_cons_round_trip"),
+    ("q_E without sqrt(gamma) (Sec 2.1)",
+     "for (int j = 0; j < 3; j++) q[5 + j] = m.sqrtg * E[j];\n}", "for (int j = 0; j < 3; j++) q[5 + j] = E[j];\n}",
+     RU + "test_fallback_state_field_and_count"),
+    ("metric derivative d gamma = 2 psi^3 d psi for 4 psi^3 d psi (Sec 2.1)",
+     "double dg = (jj == kk) ? 4.0 * ps * ps * ps * dps[a] : 0.0;",
+     "double dg = (jj == kk) ? 2.0 * ps * ps * ps * dps[a] : 0.0;",
+     SP + "test_tov_hydrostatic_residual_converges"),
+    ("lapse-gradient force -(tau + D) d alpha dropped (Sec 2.1)",
+     "L[1 + a] += m.sqrtg * (-tauD * dal[a] + sg);", "L[1 + a] += m.sqrtg * (sg);",
+     SP + "test_tov_hydrostatic_residual_converges"),
+    ("dynamo term of the at-rest field dropped (Sec 2.4)",
+     "for (int i = 0; i < 3; i++) E[i] = (Es[i] + xi * r * B[i]) / (1.0 + r);",
+     "for (int i = 0; i < 3; i++) E[i] = (Es[i]) / (1.0 + r);",
+     RU + "test_fallback_field_with_the_dynamo_term"),
+    ("GLM HLL speed without the lapse (Sec 2.5)",
+     "double sp = al * sqrt(1.0 / pow4(ps));\n    for (int v = 0; v < GLM_NV; v++)",
+     "double sp = sqrt(1.0 / pow4(ps));\n    for (int v = 0; v < GLM_NV; v++)",
+     GL + "test_glm_constant_metric_is_a_rescaled_flat_run"),
 ]
 
 

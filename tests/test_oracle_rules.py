@@ -144,6 +144,30 @@ def test_fallback_state_field_and_count(kind, metric):
         assert np.all(st.q[1 + i][sl] == 0.0)  # E x B = 0 with B = 0
 
 
+@pytest.mark.parametrize("metric", [(1.0, 1.0), (0.8, 1.2)])
+def test_fallback_field_with_the_dynamo_term(metric):
+    """the field of an atmosphere cell with the mean-field dynamo term
+    (xi != 0, B != 0) is the v = 0 solution of eq. im_E: the general
+    solve of eq. im_E (pinned against a direct 3x3 solve) at u~ = 0"""
+    alpha, psi = metric
+    eta, dt, xi = 0.02, 0.01, 0.3
+    E0 = np.array([0.3, -0.2, 0.1])
+    B0 = np.array([0.1, 0.05, -0.2])
+    s = _uniform(rho=0.9e-6, p=1e-9, E=E0, alpha=alpha, psi=psi)
+    s.eta, s.rho_atm, s.p_atm, s.atm_factor, s.xi = eta, 1e-6, 1e-9, 1.001, xi
+    s.A = None
+    s.face = np.stack([np.full(s.shape, psi ** 6 * B0[d]) for d in range(3)])
+    st = oracle.OracleState(s)
+    sl = s.interior
+    stage, _ = st.step(dt, dump_stage=0)
+    _, A, _, _ = oracle.tableau(W.SSP2)
+    want = oracle.implicit_E(psi, eta / (alpha * A[0, 0] * dt), xi, np.zeros(3), E0, B0)
+    assert np.abs(want - E0).max() > 1e-3  # the dynamo term and the relaxation both act
+    for i in range(3):
+        assert np.allclose(stage[5 + i][sl], want[i], rtol=1e-13, atol=1e-15)
+    assert np.all(stage[0][sl] == s.rho_atm) and st.nfail == 0
+
+
 def test_final_recovery_rewrites_conserved_variables():
     """or_c2p_grid (recovery with E and B known): a tau < 0 cell and a cell
     below the threshold get the fallback primitives and q_D, q_S, q_tau of the
