@@ -229,6 +229,41 @@ MUTATIONS = [
      "double sp = al * sqrt(1.0 / pow4(ps));\n    for (int v = 0; v < GLM_NV; v++)",
      "double sp = sqrt(1.0 / pow4(ps));\n    for (int v = 0; v < GLM_NV; v++)",
      GL + "test_glm_constant_metric_is_a_rescaled_flat_run"),
+    ("face conformal factor taken from one cell (Sec 2.5)",
+     "    *al = 0.5 * (A_at(c, i0) + A_at(c, i1));\n    *ps = 0.5 * (P_at(c, i0) + P_at(c, i1));",
+     "    *al = 0.5 * (A_at(c, i0) + A_at(c, i1));\n    *ps = P_at(c, i1);",
+     SP + "test_uniform_pressure_in_a_conformal_factor_is_an_equilibrium"),
+    ("face lapse taken from one cell (Sec 2.5)",
+     "    *al = 0.5 * (A_at(c, i0) + A_at(c, i1));\n    *ps = 0.5 * (P_at(c, i0) + P_at(c, i1));",
+     "    *al = A_at(c, i1);\n    *ps = 0.5 * (P_at(c, i0) + P_at(c, i1));",
+     SP + "test_killing_energy_in_static_lapse"),
+    ("face speed alpha / psi^4 for alpha / psi^2 (Sec 2.5)",
+     "return al / (ps * ps);", "return al / (ps * ps * ps * ps);",
+     SP + "test_constant_metric_is_a_rescaled_flat_run"),
+    ("E at the a-faces without psi^4 (Sec 3.2 (ii))",
+     "    *L = l * p4;\n    *R = r * p4;", "    *L = l;\n    *R = r;",
+     SP + "test_constant_metric_is_a_rescaled_flat_run"),
+    ("cell-centred B without 1/psi^6",
+     "B[d] = 0.5 * (face[d][id] + face[d][IXv(q, cp)]) / p6;", "B[d] = 0.5 * (face[d][id] + face[d][IXv(q, cp)]);",
+     RU + "test_fallback_field_with_the_dynamo_term"),
+    ("cell-centred B from one face",
+     "B[d] = 0.5 * (face[d][id] + face[d][IXv(q, cp)]) / p6;", "B[d] = face[d][id] / p6;",
+     RU + "test_final_recovery_rewrites_conserved_variables"),
+    ("stiff term R without psi^6 (Sec 2.3)",
+     "R[i][a][id] = (p6 * E[a] - qs[5 + a]) / (aii * dt);", "R[i][a][id] = (E[a] - qs[5 + a]) / (aii * dt);",
+     IM + "test_stiff_relaxation_amplification"),
+    ("stage cells with the implicit weights on L (Sec 2.3)",
+     "acc += dt * At[i * 4 + j] * Lc[j][v][id];\n                            if (v >= 5)",
+     "acc += dt * A[i * 4 + j] * Lc[j][v][id];\n                            if (v >= 5)",
+     DY + "test_closed_form_growth_k2"),
+    ("stage cells with the explicit weights on R (Sec 2.3)",
+     "if (v >= 5) acc += dt * A[i * 4 + j] * R[j][v - 5][id];",
+     "if (v >= 5) acc += dt * At[i * 4 + j] * R[j][v - 5][id];",
+     DY + "test_closed_form_growth_k2"),
+    ("reconstruction stencil shifted by one cell",
+     "        cc[d] += m - 3;\n        if (kind != RC_PPM && (m == 0 || m == 5)) { w[m] = 0.0; continue; }",
+     "        cc[d] += m - 2;\n        if (kind != RC_PPM && (m == 0 || m == 5)) { w[m] = 0.0; continue; }",
+     DY + "test_printed_growth_k1"),
 ]
 
 

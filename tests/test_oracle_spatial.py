@@ -234,6 +234,33 @@ def test_tov_hydrostatic_residual_converges():
     assert res[1] < 5e-6
 
 
+def test_uniform_pressure_in_a_conformal_factor_is_an_equilibrium():
+    """a uniform fluid at rest in a conformally flat metric with unit lapse
+    and psi linear in x: the divergence of the momentum flux psi^6 p equals
+    the metric source (1/2) sqrt(gamma) S^jk d_x gamma_jk = 6 psi^5 p d_x psi
+    (Sec 2.1), so L vanishes up to truncation error, which falls at second
+    order (faces take the mean of the two cells' psi)"""
+    res = []
+    for n in (32, 64, 128):
+        s = W.density_wave(n, ndim=1, amp=0.0, v=0.0)
+        s.bc = ((W.OUTFLOW, W.OUTFLOW),) * 3
+        s.lo, s.hi = (-1.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+        X = s.mesh()[0]
+        s.metric = 1
+        s.alpha = np.ones(s.shape)
+        s.psi = 1.0 + 0.2 * X
+        s.prim[0], s.prim[4] = 1.0, 0.1
+        for i in range(3):
+            s.E[i] = 0.0
+        s.A = None
+        s.face = np.zeros((3,) + s.shape)
+        Lc = _explicit_L(s)
+        res.append(np.abs(Lc[1][s.interior]).max())
+    rates = [math.log2(res[i] / res[i + 1]) for i in range(2)]
+    assert min(rates) >= 1.8, (res, rates)
+    assert res[-1] < 1e-5, res
+
+
 # --------------------------------------------------------------------------
 # smooth-wave convergence and the paper's convergence tables
 def test_density_wave_second_order():
