@@ -38,13 +38,7 @@
  * fallback state and field of forced atmosphere and failure cells, the ghost
  * copies, the closed-form time steps), or a property every implementation of
  * the rule has (a limited PPM parabola is monotone and keeps the cell mean).
- *
- * Parity unpinned for one choice: the edge speeds of the upwind EMF take the
- * larger of the speeds of the two faces beside the edge (Sec 3.2 (vi)).  The
- * speeds depend on the metric alone, so the two faces differ only by the
- * metric's change over one cell, and no closed form or invariant used by the
- * pins tells the larger from the smaller (the planted-mistake test shows the
- * swap going unnoticed).
+
  */
 #include <math.h>
 #include <stdlib.h>

@@ -260,6 +260,14 @@ MUTATIONS = [
      "if (v >= 5) acc += dt * A[i * 4 + j] * R[j][v - 5][id];",
      "if (v >= 5) acc += dt * At[i * 4 + j] * R[j][v - 5][id];",
      DY + "test_closed_form_growth_k2"),
+    ("edge speed along a: the slower of the two a-faces (Sec 3.2 (vi))",
+     "*ca = fmax(face_speed(c, a, c1), face_speed(c, a, c2));",
+     "*ca = fmin(face_speed(c, a, c1), face_speed(c, a, c2));",
+     SP + "test_edge_speed_is_that_of_the_faster_face"),
+    ("edge speed along b: the slower of the two b-faces (Sec 3.2 (vi))",
+     "*cb = fmax(face_speed(c, b, c3), face_speed(c, b, c4));",
+     "*cb = fmin(face_speed(c, b, c3), face_speed(c, b, c4));",
+     SP + "test_edge_speed_is_that_of_the_faster_face"),
     ("reconstruction stencil shifted by one cell",
      "        cc[d] += m - 3;\n        if (kind != RC_PPM && (m == 0 || m == 5)) { w[m] = 0.0; continue; }",
      "        cc[d] += m - 2;\n        if (kind != RC_PPM && (m == 0 || m == 5)) { w[m] = 0.0; continue; }",

@@ -204,7 +204,7 @@ def test_constant_metric_is_a_rescaled_flat_run(uct, frozen):
         assert np.abs(stA.face[d][sl] / psi ** 4 - stB.face[d][sl]).max() <= 1e-12
 
 
-def _explicit_L(s):
+def _explicit_L(s, faces=False):
     st = oracle.OracleState(s)
     cells = [st.prim[v] for v in range(5)] + [np.ascontiguousarray(st.q[5 + v] / s.psi ** 6) for v in range(3)]
     oracle.lib().or_ghost_fill(ctypes.byref(st.grid), _pp(cells), 8, _pp(st.face))
@@ -212,7 +212,57 @@ def _explicit_L(s):
     Lf = [np.zeros(s.shape) for _ in range(3)]
     oracle.lib().or_explicit_L(ctypes.byref(st.grid), _pp(cells[:5]), _pp(cells[5:]), _pp(st.face), _p(st.alpha),
                                _p(st.psi), _pp(Lc), _pp(Lf))
-    return Lc
+    return (Lc, Lf) if faces else Lc
+
+
+@pytest.mark.parametrize("side", ["a", "b"])
+def test_edge_speed_is_that_of_the_faster_face(side):
+    """Sec 3.2 (vi): an edge's speed in each direction is the larger of the
+    speeds of the two faces of that direction beside it.  A fluid at rest with
+    E = 0 and a face field that jumps across the other direction, in a lapse
+    growing across it (side a: q_B^y jumping across x = 0, lapse growing in
+    y; side b: q_B^x jumping across y = 0, lapse growing in x): the EMF of a
+    z-edge is then one dissipation term alone, so the face update of that
+    field along each row (column) of faces equals, bit for bit, that of a
+    constant lapse equal to the lapse of the cell above (to the right), the
+    faster face"""
+    n = 12
+    d, t = (1, 0) if side == "a" else (0, 1)  # field direction, jump direction
+
+    def setup(alpha_of):
+        s = W.density_wave(n, ndim=2, amp=0.0, v=0.0)
+        s.bc = ((W.OUTFLOW, W.OUTFLOW),) * 3
+        s.lo, s.hi = (-1.0, -1.0, 0.0), (1.0, 1.0, 1.0)
+        M = s.mesh()
+        s.metric = 1
+        s.alpha = alpha_of(M[d])
+        s.psi = np.ones(s.shape)
+        s.prim[0], s.prim[4] = 1.0, 0.1
+        for i in range(3):
+            s.E[i] = 0.0
+        s.A = None
+        s.face = np.zeros((3,) + s.shape)
+        s.face[d] = np.where(M[t] > 0.0, 0.1, -0.1)  # a function of the other coordinate only
+        return s
+
+    def lapse(x):
+        return 1.0 + 0.15 * (x + 1.0)
+
+    s = setup(lapse)
+    _, Lf = _explicit_L(s, faces=True)
+    g = s.g(d)
+    xc = s.mesh()[d][0, :, :]
+    changed = 0
+    for j in range(g + 1, g + n):  # faces between cells j - 1 and j along d
+        up = lapse(xc[j, g] if d == 1 else xc[g, j])
+        _, Lf_c = _explicit_L(setup(lambda x: np.full(x.shape, up)), faces=True)
+        if d == 1:
+            mine, ref = Lf[1][:, j, g:g + n], Lf_c[1][:, j, g:g + n]
+        else:
+            mine, ref = Lf[0][:, g:g + n, j], Lf_c[0][:, g:g + n, j]
+        assert np.array_equal(mine, ref), j
+        changed += int(np.abs(mine).max() > 0.0)
+    assert changed == n - 1
 
 
 def test_tov_hydrostatic_residual_converges():
