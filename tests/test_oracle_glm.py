@@ -237,3 +237,21 @@ def test_glm_constant_metric_is_a_rescaled_flat_run():
     for v in (8, 9):
         assert np.abs(stA.q[v][sl] / psi ** 6 - stB.q[v][sl]).max() <= 1e-12 * bsc, v
         assert np.abs(stB.q[v][sl]).max() > 1e-6 * bsc, v  # Psi and Phi do develop
+
+
+def test_div_b_norms_of_cell_centred_field():
+    """cell-centred q_B^x = sin(kx) on a periodic line: the central difference
+    of the sine is cos(k x) sin(k dx) / dx exactly; the three norms are the
+    mean of its magnitude, the root mean square and the maximum"""
+    s = W.glm_wave(40, k=1, kappa=1.0)
+    st = oracle.OracleState(s)
+    X = s.mesh()[0]
+    h = s.dx(0)
+    st.face[0][...] = np.sin(X)
+    st.face[1][...] = 0.0
+    st.face[2][...] = 0.0
+    div = (np.cos(X) * math.sin(h) / h)[s.interior]
+    got = st.divB()
+    assert got[0] == pytest.approx(np.abs(div).mean(), rel=1e-12)
+    assert got[1] == pytest.approx(math.sqrt((div ** 2).mean()), rel=1e-12)
+    assert got[2] == pytest.approx(np.abs(div).max(), rel=1e-12)

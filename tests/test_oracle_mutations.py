@@ -268,6 +268,35 @@ MUTATIONS = [
      "*cb = fmax(face_speed(c, b, c3), face_speed(c, b, c4));",
      "*cb = fmin(face_speed(c, b, c3), face_speed(c, b, c4));",
      SP + "test_edge_speed_is_that_of_the_faster_face"),
+    ("L1 norm of div B summed, not averaged (eq. divb_0)",
+     "    out[0] = s1 / cnt;\n    out[1] = sqrt(s2 / cnt);\n    out[2] = mx;\n}\n\n\n",
+     "    out[0] = s1;\n    out[1] = sqrt(s2 / cnt);\n    out[2] = mx;\n}\n\n\n",
+     SP + "test_div_b_norms_of_a_known_divergence"),
+    ("face divergence with a sum for a difference (eq. divb_0)",
+     "dv += (face[d][IXv(&q, cp)] - face[d][id]) / q.dx[d];", "dv += (face[d][IXv(&q, cp)] + face[d][id]) / q.dx[d];",
+     SP + "test_div_b_norms_of_a_known_divergence"),
+    ("cell-centred divergence without the 1/2 of the central difference",
+     "dv += (tmp[d][IXv(&q, cp)] - tmp[d][IXv(&q, cm)]) / (2.0 * q.dx[d]);",
+     "dv += (tmp[d][IXv(&q, cp)] - tmp[d][IXv(&q, cm)]) / (q.dx[d]);",
+     GL + "test_div_b_norms_of_cell_centred_field"),
+    ("recovery: E x B not removed from S (Sec 2.6)",
+     "for (int j = 0; j < 3; j++) Sf[j] = S[j] - ExB[j];", "for (int j = 0; j < 3; j++) Sf[j] = S[j];",
+     PT + "test_prim_cons_round_trip"),
+    ("recovery: electromagnetic energy not removed from tau (Sec 2.6)",
+     "double tauf = tau - UEM;", "double tauf = tau;",
+     IM + "test_stiff_relaxation_amplification"),
+    ("recovery: u~ without its factor W (Sec 2.6)",
+     "for (int i = 0; i < 3; i++) prim[1 + i] = W * Sfu[i] / Z;", "for (int i = 0; i < 3; i++) prim[1 + i] = Sfu[i] / Z;",
+     PT + "test_prim_cons_round_trip"),
+    ("recovery: rho = D (Sec 2.6)",
+     "prim[0] = D / W;", "prim[0] = D;",
+     PT + "test_prim_cons_round_trip"),
+    ("CFL speed without 1/psi^2 (Sec 2.5)",
+     "if (q.act[d]) s += al * sqrt(1.0 / pow4(ps)) / q.dx[d];", "if (q.act[d]) s += al / q.dx[d];",
+     RU + "test_cfl_dt_constant_metric_is_rescaled_flat_step"),
+    ("CFL speed without the lapse (Sec 2.5)",
+     "if (q.act[d]) s += al * sqrt(1.0 / pow4(ps)) / q.dx[d];", "if (q.act[d]) s += sqrt(1.0 / pow4(ps)) / q.dx[d];",
+     RU + "test_cfl_dt_constant_metric_is_rescaled_flat_step"),
     ("reconstruction stencil shifted by one cell",
      "        cc[d] += m - 3;\n        if (kind != RC_PPM && (m == 0 || m == 5)) { w[m] = 0.0; continue; }",
      "        cc[d] += m - 2;\n        if (kind != RC_PPM && (m == 0 || m == 5)) { w[m] = 0.0; continue; }",

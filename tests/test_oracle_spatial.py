@@ -455,3 +455,25 @@ def test_killing_energy_in_static_lapse():
         drift.append(abs(e1 - e0) / e0)
     assert drift[1] < drift[0] / 3
     assert drift[1] < 1e-5, drift
+
+
+def test_div_b_norms_of_a_known_divergence():
+    """face field q_B^x = x^2 + y, q_B^y = x y^2 on a 2-D grid: the face
+    difference of a quadratic is its derivative at the cell centre, so the
+    discrete divergence there is exactly 2x + 2xy; the three norms are the
+    mean of its magnitude, the root mean square and the maximum over the
+    interior cells"""
+    s = W.density_wave(10, ndim=2, amp=0.0, v=0.0)
+    s.lo, s.hi = (-1.0, -0.5, 0.0), (1.0, 1.5, 1.0)
+    st = oracle.OracleState(s)
+    X, Y, _ = s.mesh()
+    hx, hy = s.dx(0), s.dx(1)
+    st.face[0][...] = (X - 0.5 * hx) ** 2 + Y
+    st.face[1][...] = X * (Y - 0.5 * hy) ** 2
+    st.face[2][...] = 0.0
+    sl = s.interior
+    div = (2.0 * X + 2.0 * X * Y)[sl]
+    got = st.divB()
+    assert got[0] == pytest.approx(np.abs(div).mean(), rel=1e-12)
+    assert got[1] == pytest.approx(math.sqrt((div ** 2).mean()), rel=1e-12)
+    assert got[2] == pytest.approx(np.abs(div).max(), rel=1e-12)
